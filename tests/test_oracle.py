@@ -1,0 +1,349 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics and the paper.
+
+Each test checks the oracle against something other than itself: exact
+rational element matrices, a solution that lies in the Q2 space, convergence
+rates of a manufactured solution, the fixed point of the Schwarz iteration,
+an exact energy identity, closed-form contraction factors, and Table 1.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import assemble as A
+from oracle import direct as D
+from oracle import fe, fourier
+from oracle import mesh as M
+from oracle import partition as P
+from oracle import schwarz as S
+from oracle import subdomain as SD
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def phi_q2(x, y, z):
+    return x * (1 - x) * y * (1 - y) * z * (1 - z)
+
+
+def f_q2(x, y, z):
+    # -Laplacian of phi_q2
+    return 2.0 * (y * (1 - y) * z * (1 - z) + x * (1 - x) * z * (1 - z) + x * (1 - x) * y * (1 - y))
+
+
+# --------------------------------------------------------------------------- elements
+
+@pytest.mark.parametrize("h", [1.0, 0.25, 1.0 / 48])
+def test_1d_element_exact_rationals(h):
+    K, Mm, l = fe.element_matrices_1d(h)
+    K_exact = np.array([[7, -8, 1], [-8, 16, -8], [1, -8, 7]]) / (3.0 * h)
+    M_exact = np.array([[4, 2, -1], [2, 16, 2], [-1, 2, 4]]) * (h / 30.0)
+    np.testing.assert_allclose(K, K_exact, rtol=1e-14, atol=1e-14 / h)
+    np.testing.assert_allclose(Mm, M_exact, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(l, h * np.array([1 / 6, 2 / 3, 1 / 6]), rtol=1e-14)
+
+
+def test_3d_element_invariants():
+    h = (0.3, 0.4, 0.5)
+    K, Mm, l = fe.element_matrices(h)
+    assert np.abs(K - K.T).max() < 1e-15 * np.abs(K).max()
+    assert np.abs(K.sum(axis=1)).max() < 1e-13  # constants are in the kernel
+    np.testing.assert_allclose(Mm.sum(), np.prod(h), rtol=1e-14)
+    np.testing.assert_allclose(l.sum(), np.prod(h), rtol=1e-14)
+    # a linear function u = x has energy int |grad u|^2 = volume
+    xs = np.array([0.0, 0.5, 1.0]) * h[0]
+    a = np.arange(27)
+    u = xs[a % 3]
+    np.testing.assert_allclose(u @ K @ u, np.prod(h), rtol=1e-13)
+    # tensor-product identity K_e = Kx(x)My(x)Mz + Mx(x)Ky(x)Mz + Mx(x)My(x)Kz
+    k = [fe.element_matrices_1d(v)[:2] for v in h]
+    (kx, mx), (ky, my), (kz, mz) = k
+    kron = np.kron(mz, np.kron(my, kx)) + np.kron(mz, np.kron(ky, mx)) + np.kron(kz, np.kron(my, mx))
+    np.testing.assert_allclose(K, kron, rtol=0, atol=1e-14 * np.abs(K).max())
+
+
+def test_face_mass_is_tangential_mass_product():
+    h = (0.3, 0.4, 0.5)
+    k = [fe.element_matrices_1d(v)[1] for v in h]
+    for axis in range(3):
+        for side in (0, 1):
+            F = fe.face_mass_side(h, axis, side)
+            a = np.arange(27)
+            pos = [a % 3, (a // 3) % 3, a // 9]
+            on = pos[axis] == 2 * side
+            ta, tb = [d for d in range(3) if d != axis]
+            exp = np.zeros((27, 27))
+            ii = np.flatnonzero(on)
+            for i in ii:
+                for j in ii:
+                    exp[i, j] = k[ta][pos[ta][i], pos[ta][j]] * k[tb][pos[tb][i], pos[tb][j]]
+            np.testing.assert_allclose(F, exp, rtol=0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------- assembly
+
+def test_assembled_stiffness_symmetric_and_matrix_free_agree():
+    m = M.BoxMesh((3, 4, 2), (1.0, 2.0, 0.5), (0, 1, 0, 0, 1, 0))
+    K = A.assemble_stiffness(m)
+    assert abs(K - K.T).max() <= 1e-15 * abs(K).max()
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(m.n_nodes)
+    np.testing.assert_allclose(A.apply_stiffness(m, u), K @ u, rtol=1e-12, atol=1e-12)
+
+
+def test_reduced_stiffness_equals_kronecker_sum_of_1d_factors():
+    m = M.BoxMesh((3, 2, 4), (1.0, 0.7, 1.3), (0, 1, 1, 0, 0, 0))
+    K, free = A.reduced_stiffness(m)
+    fac = []
+    for d in range(3):
+        lo = 1 if m.bc[2 * d] == 0 else 0
+        hi = 2 * m.ne[d] - (1 if m.bc[2 * d + 1] == 0 else 0)
+        fac.append(D.assemble_1d(m.ne[d], m.h[d], lo, hi))
+    (kx, mx), (ky, my), (kz, mz) = fac
+    kron = np.kron(mz, np.kron(my, kx)) + np.kron(mz, np.kron(ky, mx)) + np.kron(kz, np.kron(my, mx))
+    np.testing.assert_allclose(K.toarray(), kron, rtol=0, atol=1e-13 * np.abs(kron).max())
+    # positive definite with Dirichlet on part of the boundary
+    assert np.linalg.eigvalsh(K.toarray()).min() > 0
+
+
+def test_density_load_closed_form_and_ownership_split():
+    m = M.BoxMesh((2, 2, 2), (1.0, 1.0, 1.0))
+    G = 6.672e-11
+    drho = np.zeros(m.n_elem)
+    drho[5] = 3.0  # element (1, 0, 1)
+    f = A.load_from_density(m, drho, G)
+    w = np.array([1 / 6, 2 / 3, 1 / 6]) * 0.5
+    local = 4 * np.pi * G * 3.0 * np.einsum("i,j,k->kji", w, w, w).ravel()
+    conn = m.element_nodes()[5]
+    np.testing.assert_allclose(f[conn], local, rtol=1e-14)
+    assert np.count_nonzero(f) == 27
+    # constant density: load equals the function load of the constant
+    f1 = A.load_from_density(m, np.full(m.n_elem, 2.0), G)
+    f2 = A.load_from_function(m, lambda x, y, z: 4 * np.pi * G * 2.0 + 0 * x)
+    np.testing.assert_allclose(f1, f2, rtol=1e-13)
+    # subdomain loads by element ownership sum to the global load
+    m = M.BoxMesh((4, 6, 3))
+    part = P.BoxPartition(m, ((1,), (2, 4), (1,)))
+    drho = np.random.default_rng(0).uniform(-1, 1, m.n_elem)
+    f = A.load_from_density(m, drho, G)
+    acc = np.zeros(m.n_nodes)
+    for sub in part.subs:
+        acc[part.local_nodes(sub)] += SD.density_load(part, sub, drho, G)
+    free = m.unknowns()
+    np.testing.assert_allclose(acc[free], f[free], rtol=1e-12, atol=1e-25)
+
+
+# --------------------------------------------------------------------------- direct solvers
+
+@pytest.mark.parametrize("ne,L", [((2, 2, 2), (1, 1, 1)), ((3, 5, 4), (1, 1, 1)), ((6, 2, 3), (1, 1, 1))])
+def test_q2_exact_solution_direct(ne, L):
+    """x(1-x)y(1-y)z(1-z) lies in the Q2 space: the Galerkin solution is exact."""
+    m = M.BoxMesh(ne, L)
+    f = A.load_from_function(m, f_q2)
+    X = m.node_coords()
+    ex = phi_q2(X[:, 0], X[:, 1], X[:, 2])
+    for method in ("lu", "fdm"):
+        u = D.solve_direct(m, f, method)
+        assert np.abs(u - ex).max() < 1e-14, method
+
+
+def test_lu_and_fdm_agree_mixed_boundary():
+    m = M.BoxMesh((5, 4, 6), (1.0, 0.8, 1.5), (0, 1, 0, 0, 1, 0))
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(m.n_nodes)
+    u1 = D.solve_direct(m, f, "lu")
+    u2 = D.solve_direct(m, f, "fdm")
+    assert np.abs(u1 - u2).max() <= 1e-12 * np.abs(u1).max()
+
+
+def _errors(m, u):
+    X, uq, gq, w = A.interpolate(m, u, nq=5)
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    pi = np.pi
+    ex = np.sin(pi * x) * np.sin(pi * y) * np.sin(pi * z)
+    gx = pi * np.cos(pi * x) * np.sin(pi * y) * np.sin(pi * z)
+    gy = pi * np.sin(pi * x) * np.cos(pi * y) * np.sin(pi * z)
+    gz = pi * np.sin(pi * x) * np.sin(pi * y) * np.cos(pi * z)
+    l2 = np.sqrt(np.sum((uq - ex) ** 2 * w))
+    h1 = np.sqrt(np.sum(((gq[..., 0] - gx) ** 2 + (gq[..., 1] - gy) ** 2 + (gq[..., 2] - gz) ** 2) * w))
+    return l2, h1
+
+
+def test_manufactured_solution_convergence_rates():
+    """Phi = sin(pi x) sin(pi y) sin(pi z), f = 3 pi^2 Phi: Q2 gives L2 error
+    O(h^3) and H1 error O(h^2)."""
+    pi = np.pi
+    errs = []
+    Ns = (4, 8, 16, 24)
+    for N in Ns:
+        m = M.BoxMesh((N, N, N))
+        f = A.load_from_function(
+            m, lambda x, y, z: 3 * pi * pi * np.sin(pi * x) * np.sin(pi * y) * np.sin(pi * z), nq=5)
+        u = D.solve_direct(m, f, "fdm")
+        errs.append(_errors(m, u))
+    errs = np.array(errs)
+    hs = 1.0 / np.array(Ns)
+    rates = np.log(errs[1:] / errs[:-1]) / np.log(hs[1:, None] / hs[:-1, None])
+    assert np.all(np.abs(rates[1:, 0] - 3.0) < 0.15), rates
+    assert np.all(np.abs(rates[1:, 1] - 2.0) < 0.15), rates
+
+
+# --------------------------------------------------------------------------- partition
+
+def test_partition_counts_of_named_workloads():
+    from synth import workload
+    expect = {"c1": (4, 8, 31744, 29791), "c2": (64, 288, 2197000, 2048383),
+              "c4": (27, 108, None, None)}
+    for name, (nsub, nface, nloc, nglob) in expect.items():
+        wl = workload(name)
+        m = M.BoxMesh(wl.ne, wl.lengths, wl.bc)
+        part = P.BoxPartition(m, wl.cuts)
+        assert part.n_sub == nsub and len(part.faces) == nface
+        if nloc is not None:
+            assert sum(s.n for s in part.subs) == nloc
+            assert m.unknowns().size == nglob
+    wl = workload("c3", seed=0)
+    m = M.BoxMesh(wl.ne, wl.lengths, wl.bc)
+    part = P.BoxPartition(m, wl.cuts)
+    assert part.n_sub == 256 and len(part.faces) == 960
+    closure = [np.prod([2 * (s.e1[d] - s.e0[d]) + 1 for d in range(3)]) for s in part.subs]
+    assert 2425 <= min(closure) and max(closure) <= 35017
+    assert m.unknowns().size == 3465695
+
+
+def test_faces_pair_up():
+    m = M.BoxMesh((4, 6, 4), bc=(0, 0, 1, 0, 0, 1))
+    part = P.BoxPartition(m, ((2,), (1, 3), (2,)))
+    for f in part.faces:
+        g = part.faces[part.face_index[(f.j, f.s)]]
+        assert g.axis == f.axis and g.side == 1 - f.side
+        np.testing.assert_array_equal(f.nodes, g.nodes)
+        Mf, Mg = SD.face_mass_local(part, f), SD.face_mass_local(part, g)
+        assert abs(Mf - Mg).max() < 1e-17
+
+
+def test_subdomain_matrix_is_kronecker_sum_with_robin_ends():
+    m = M.BoxMesh((4, 4, 3), bc=(0, 0, 1, 0, 0, 0))
+    part = P.BoxPartition(m, ((2,), (1,), (1,)))
+    p = 7.5
+    orc = S.SchwarzOracle(part, p, "lu")
+    for sub in part.subs:
+        As = SD.robin_matrix(part, sub, lambda f: p).toarray()
+        _, fac = orc._fdm_factors(sub)
+        (kx, mx), (ky, my), (kz, mz) = fac
+        kron = np.kron(mz, np.kron(my, kx)) + np.kron(mz, np.kron(ky, mx)) + np.kron(kz, np.kron(my, mx))
+        np.testing.assert_allclose(As, kron, rtol=0, atol=1e-13 * np.abs(kron).max())
+
+
+# --------------------------------------------------------------------------- Schwarz
+
+def test_schwarz_fixed_point_is_global_solution_with_cross_points():
+    from synth.generators import uniform_density
+    m = M.BoxMesh((6, 6, 4))
+    part = P.BoxPartition(m, ((3,), (2, 4), (2,)))  # 2x3x2, edges and corners shared
+    G = 6.672e-11
+    drho = uniform_density(m.ne, seed=5)
+    f = A.load_from_density(m, drho, G)
+    fs = [SD.density_load(part, s, drho, G) for s in part.subs]
+    orc = S.SchwarzOracle(part, 8.0 / m.h[0], "lu")
+    U, n, res, _ = orc.solve(fs, f, 1e-12, 5000)
+    ud = D.solve_direct(m, f, "lu")
+    assert res <= 1e-12
+    assert np.abs(U - ud).max() <= 1e-10 * np.abs(ud).max()
+
+
+def test_schwarz_reproduces_q2_exact_solution():
+    m = M.BoxMesh((4, 4, 6))
+    part = P.BoxPartition(m, ((2,), (1,), (2, 4)))
+    f = A.load_from_function(m, f_q2)
+    orc = S.SchwarzOracle(part, 2.0 / m.h[0], "fdm")
+    U, n, res, _ = orc.solve(SD.split_load(part, f), f, 1e-13, 5000)
+    X = m.node_coords()
+    assert np.abs(U - phi_q2(X[:, 0], X[:, 1], X[:, 2])).max() < 1e-13
+
+
+def test_schwarz_energy_identity():
+    """f = 0: sum ||lambda^n||^2_{M^-1} - sum ||lambda^{n+1}||^2_{M^-1}
+    = 4 p sum_s u_s^T K_s^N u_s (symmetric p)."""
+    m = M.BoxMesh((4, 4, 4))
+    part = P.BoxPartition(m, ((2,), (2,), (2,)))
+    p = 11.0
+    orc = S.SchwarzOracle(part, p, "lu")
+    rng = np.random.default_rng(7)
+    lam = [rng.standard_normal(f.nodes.size) for f in part.faces]
+    zeros = [np.zeros(s.n) for s in part.subs]
+    KN = [SD.neumann_stiffness(part, s) for s in part.subs]
+    Minv = [np.linalg.inv(Mf.toarray()) for Mf in orc.M]
+
+    def energy(l):
+        return sum(li @ Mi @ li for li, Mi in zip(l, Minv))
+
+    for _ in range(3):
+        u = orc.subdomain_solves(zeros, lam)
+        new = orc.exchange(u, lam)
+        lhs = energy(lam) - energy(new)
+        rhs = 4 * p * sum(us @ (K @ us) for us, K in zip(u, KN))
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-10)
+        lam = new
+
+
+def test_two_subdomain_mode_contraction_closed_form():
+    """Unit cube split in two along x, f = 0, one tangential mode: the Robin
+    datum is multiplied by (p - S)/(p + S) every iteration."""
+    nx, ny = 8, 6
+    m = M.BoxMesh((2 * nx, ny, ny))
+    part = P.BoxPartition(m, ((nx,), (), ()))
+    p = 9.0
+    orc = S.SchwarzOracle(part, p, "lu")
+    muy, Vy = fourier.tangential_modes(ny, m.h[1], 1, 2 * ny - 1)
+    iy, iz = 1, 2
+    v = np.kron(Vy[:, iz], Vy[:, iy])
+    mu = muy[iy] + muy[iz]
+    Mf = orc.M[0].toarray()
+    lam = [Mf @ v, Mf @ v]
+    zeros = [np.zeros(s.n) for s in part.subs]
+    S_ = fourier.schur_interface(nx, m.h[0], mu)
+    factor = (p - S_) / (p + S_)
+    for _ in range(4):
+        u = orc.subdomain_solves(zeros, lam)
+        new = orc.exchange(u, lam)
+        for a, b in zip(lam, new):
+            np.testing.assert_allclose(b, factor * a, rtol=1e-9, atol=1e-12 * np.abs(a).max())
+        lam = new
+    assert abs(fourier.rho_discrete_two(nx, m.h[0], mu, p) - factor ** 2) < 1e-14
+
+
+def test_discrete_factor_tends_to_continuous_symbol():
+    """The discrete Schur symbol tends to k coth(k a); for a deep subdomain the
+    factor is the half-space |(k - p)/(k + p)|^2."""
+    p = 12.0
+    for depth, nxe in ((0.5, 24), (3.0, 96)):
+        n_t = 24
+        mu, _ = fourier.tangential_modes(n_t, 1.0 / n_t, 1, 2 * n_t - 1)
+        kk = np.sqrt(mu[0] + mu[0])  # mode (1, 1)
+        disc = fourier.rho_discrete_two(nxe, depth / nxe, kk * kk, p)
+        cont = fourier.rho_finite_depth(kk, p, depth)
+        assert abs(disc - cont) < 1e-6 * cont
+    k = np.pi * np.sqrt(2)
+    half = fourier.rho_halfspace(k, p)
+    np.testing.assert_allclose(half, ((k - p) / (k + p)) ** 2, rtol=1e-15)
+    assert abs(fourier.rho_finite_depth(k, p, 3.0) - half) < 1e-6
+
+
+def test_table1_rates_reproduced():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_cmaes.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                name, *vals = line.split()
+                rows.append((name, [float(v) for v in vals]))
+    assert len(rows) == 4
+    for name, (p1, q1, p2, q2, rmax) in rows:
+        got = fourier.rho_max(p1, q1, p2, q2, 0.0174, 1.0)
+        assert abs(got / rmax - 1.0) < 0.014, (name, got, rmax)
+    # the opposite sign of the second-order term gives rates above one
+    p1, q1, p2, q2, _ = rows[2][1]
+    k = np.linspace(0.0174, 1.0, 1001)
+    bad = np.abs((k - p1 + q1 * k * k) * (k - p2 + q2 * k * k) /
+                 ((k + p1 - q1 * k * k) * (k + p2 - q2 * k * k)))
+    assert bad.max() > 1.0

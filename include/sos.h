@@ -1,0 +1,191 @@
+/*
+ * sos.h -- optimized Schwarz subdomain solves for the gravity equation on one
+ * MI355X (gfx950).
+ *
+ * Problem (Sec. 2): Delta(Phi) = -4 pi G drho on a box, discretised with 27-node
+ * Q2 hexahedra on an nx*ny*nz grid of equal box elements, homogeneous Dirichlet
+ * or Neumann data per outer face.
+ * Method (Sec. 3): non-overlapping Schwarz iteration with Robin transmission
+ * conditions of zeroth order (operator p), Jacobi order, one Robin datum per
+ * directed interface face, exchanged after every outer iteration. Every outer
+ * iteration solves all subdomain problems with diagonally preconditioned
+ * conjugate gradients (Sec. 6), on the GPU.
+ *
+ * Conventions
+ *   - Every function returns 0 (SOS_OK) or a negative error code; none throws
+ *     or aborts. sos_last_error() describes the last failure of the calling
+ *     thread.
+ *   - Element arrays: length nx*ny*nz, index ex + nx*(ey + ny*ez).
+ *   - Node arrays: length (2nx+1)(2ny+1)(2nz+1), index ix + Nx*(iy + Ny*iz),
+ *     Nx = 2nx+1, Ny = 2ny+1 (element vertices plus edge, face and cell
+ *     mid-points).
+ *   - Subdomain s = px + Px*(py + Py*pz). Directed face (s <- j) carries the
+ *     Robin datum s receives from neighbour j; faces are numbered by s, then
+ *     axis (x, y, z), then side (lower, upper). See sos_faces().
+ *   - Pointers inside the descriptor structs are HOST pointers. Pointer
+ *     arguments of sos_solve/sos_solve_load/sos_apply_local/sos_get_state/
+ *     sos_set_state are DEVICE pointers on the context's device, caller-owned,
+ *     contiguous, FP64 unless stated. Work is enqueued on opts.stream.
+ *   - The library allocates its workspaces in sos_setup and frees them in
+ *     sos_destroy. A context is not thread-safe; one context per stream.
+ */
+#ifndef SOS_H
+#define SOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sos_ctx sos_ctx; /* opaque, owned by the library */
+
+enum {
+  SOS_OK = 0,
+  SOS_EINVAL = -1,      /* bad argument or unsupported geometry             */
+  SOS_ENOMEM = -2,      /* device or host allocation failed                 */
+  SOS_EHIP = -3,        /* a HIP runtime call failed                        */
+  SOS_ENOCONV = -4,     /* max_outer reached; phi and stats still written   */
+  SOS_EBREAKDOWN = -5,  /* non-positive p'Ap or a non-finite value in a CG  */
+  SOS_ESTATE = -6       /* call out of order (e.g. no GPU, context unusable)*/
+};
+
+enum { SOS_DIRICHLET = 0, SOS_NEUMANN = 1 };
+
+/* Arithmetic of the inner subdomain solves. The Robin data, the subdomain
+ * iterates, the local residuals and the global residual are always FP64. */
+enum { SOS_FP64 = 0, SOS_FP32_INNER = 1 };
+
+/* How the inner CG solves are launched.
+ *   SOS_STEPWISE: the host drives every CG step; one launch per step covers
+ *                 all subdomains (apply + p'q, then update + r'z, r'r).
+ *   SOS_BATCHED:  one fused kernel per outer iteration runs every subdomain's
+ *                 complete CG solve (each workgroup owns a subdomain and
+ *                 stops on its own criterion), and the outer iterations
+ *                 between two convergence checks are replayed as one HIP
+ *                 graph when use_graph is set. */
+enum { SOS_STEPWISE = 0, SOS_BATCHED = 1 };
+
+typedef struct {
+  int32_t ne[3];    /* elements per axis, >= 1                               */
+  double len[3];    /* box lengths, > 0                                      */
+  int32_t bc[6];    /* x-, x+, y-, y+, z-, z+ : SOS_DIRICHLET or SOS_NEUMANN  */
+} sos_mesh;
+
+typedef struct {
+  int32_t nparts[3];      /* subdomains per axis, 1 <= nparts[d] <= ne[d]     */
+  const int32_t* cuts[3]; /* nparts[d]-1 strictly increasing element indices
+                             in (0, ne[d]); NULL = equal split (ne divisible) */
+} sos_partition;
+
+typedef struct {
+  int32_t order;     /* 0: zeroth order, operator p (the only order built)    */
+  double p0;         /* Robin coefficient of every directed face if p == NULL */
+  const double* p;   /* optional: per directed face, sos_faces() order, > 0   */
+} sos_robin;
+
+typedef struct {
+  int32_t precision;   /* SOS_FP64 or SOS_FP32_INNER                          */
+  int32_t mode;        /* SOS_STEPWISE or SOS_BATCHED                         */
+  int32_t max_outer;   /* outer iteration limit (default 100000)              */
+  int32_t max_inner;   /* CG iteration limit per subdomain solve (default 500)*/
+  int32_t check_every; /* outer iterations between global residual checks (1)*/
+  int32_t use_graph;   /* SOS_BATCHED only: replay check_every iterations as a
+                          HIP graph (default 1)                               */
+  double inner_tol;    /* CG stop: ||r_k|| <= inner_tol * ||r_0||, r_0 the
+                          local residual of the current outer iterate
+                          (default 1e-2 for FP32_INNER, 0 for FP64)           */
+  double inner_abs;    /* and/or ||r_k|| <= inner_abs * ||b_s||, b_s the local
+                          right-hand side (default 1e-10 for FP64, 0 for FP32)*/
+  double G;            /* gravitational constant (default 6.672e-11, Sec. 2)  */
+  void* stream;        /* hipStream_t; NULL = default stream                  */
+  int32_t block;       /* SOS_BATCHED workgroup size (0 = autotune)            */
+  int32_t timing;      /* 1: time every fused-kernel launch with HIP events
+                          (launches eagerly: events inside a graph are not
+                          readable)                                           */
+} sos_opts;
+
+typedef struct {
+  int32_t outer_iters;    /* outer iterations performed                         */
+  int32_t checks;         /* global residual evaluations                        */
+  int64_t inner_iters;    /* CG iterations summed over subdomain solves         */
+  double rel_residual;    /* ||f - K u||_2 / ||f||_2 over unknowns at the end   */
+  double seconds;         /* wall time of the solve                             */
+  double kernel_ms;       /* timing = 1: summed duration of the fused CG kernel
+                             (SOS_BATCHED) or of the CG step kernels (STEPWISE) */
+  int64_t kernel_launches;/* number of launches summed in kernel_ms             */
+  double kernel_bytes;    /* algorithmic bytes of those launches (per CG
+                             iteration and local unknown: 10 words read/written
+                             + the per-solve setup and update)   */
+  int32_t block;          /* workgroup size used by the fused CG kernel         */
+} sos_stats;
+
+/* Fill *opts with defaults for the given precision. */
+int sos_opts_default(sos_opts* opts, int32_t precision);
+
+/* Validate mesh/partition/Robin data, build subdomain and face descriptors,
+ * allocate device workspaces on the current HIP device. Every subdomain's
+ * x-y node plane ((2*ex+1)*(2*ey+1), ex, ey its element counts) must hold at
+ * most 4096 nodes (SOS_EINVAL otherwise). */
+int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* robin,
+              const sos_opts* opts, sos_ctx** out);
+
+/* Replace the Robin coefficients (same partition). */
+int sos_set_robin(sos_ctx* ctx, const sos_robin* robin);
+
+/* Replace the run options (precision is fixed at setup). */
+int sos_set_opts(sos_ctx* ctx, const sos_opts* opts);
+
+/* Number of directed faces; if s_j_axis != NULL it receives 4 int32 per face:
+ * s, j, axis, side (host memory, 4*n entries). */
+int sos_faces(const sos_ctx* ctx, int32_t* n, int32_t* s_j_axis_side);
+
+/* Layout of the concatenated subdomain vectors: n_sub; if offsets != NULL it
+ * receives n_sub+1 int64 offsets, if dims != NULL 3*n_sub int32 local node
+ * counts (x, y, z) and if lo != NULL 3*n_sub int32 global node indices of
+ * each subdomain's first local node. Local node (i, j, k) of s sits at
+ * offsets[s] + i + nx*(j + ny*k). Face f's datum (sos_get_state) sits at
+ * face_off[f] if face_off != NULL (n_faces+1 int64). */
+int sos_layout(const sos_ctx* ctx, int32_t* n_sub, int64_t* offsets, int32_t* dims,
+               int32_t* lo, int64_t* face_off);
+
+/* Solve with the load of a per-element density anomaly drho (kg/m^3):
+ * f_s = 4 pi G sum over s's own elements of drho_e int phi_i. Iterates until
+ * the global relative residual ||f - K u~||/||f|| <= tol (checked every
+ * check_every outer iterations; u~ the average of the subdomain copies) and
+ * writes u~ to phi_nodes (0 on Dirichlet nodes). Starts from u = 0, lambda = 0.
+ * Returns SOS_ENOCONV if max_outer is reached, or if the best residual has not
+ * improved by 1% for 2000 outer iterations (stagnation, e.g. a tol below the
+ * floor that an absolute inner tolerance leaves); phi and stats are still
+ * written. */
+int sos_solve(sos_ctx* ctx, const double* drho_elem, double tol, double* phi_nodes,
+              sos_stats* stats);
+
+/* Same with a nodal load f (the weak right-hand side over all nodes; values on
+ * Dirichlet nodes ignored), split among the subdomain copies of every node in
+ * equal parts. */
+int sos_solve_load(sos_ctx* ctx, const double* f_nodes, double tol, double* phi_nodes,
+                   sos_stats* stats);
+
+/* Diagnostics used by the parity tests. */
+/* y_s = A_s x_s for every subdomain s (concatenated local layout, device).
+ * precision selects the FP64 (x, y double*) or FP32 (float*) operator. */
+int sos_apply_local(sos_ctx* ctx, int32_t precision, const void* x, void* y);
+/* Copy the outer state out of / into the context: u (local layout, FP64) and
+ * lambda (face_off layout, FP64). Either pointer may be NULL. */
+int sos_get_state(sos_ctx* ctx, double* u_local, double* lambda);
+int sos_set_state(sos_ctx* ctx, const double* u_local, const double* lambda);
+/* Load f_s from drho (as sos_solve) without iterating. */
+int sos_set_density(sos_ctx* ctx, const double* drho_elem);
+/* Run n outer iterations from the current state with the current load. */
+int sos_iterate(sos_ctx* ctx, int32_t n, sos_stats* stats);
+/* Global relative residual and glued solution of the current state. */
+int sos_residual(sos_ctx* ctx, double* phi_nodes, double* rel_residual);
+
+void sos_destroy(sos_ctx* ctx);
+const char* sos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOS_H */

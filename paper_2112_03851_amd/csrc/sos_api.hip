@@ -1,0 +1,826 @@
+// C-ABI of the Robin-Schwarz subdomain-solve library: validation, descriptors,
+// workspaces, the outer iteration (Sec. 3) and its convergence check.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sos.h"
+#include "sos_internal.h"
+#include "sos_kernels.h"
+
+using namespace sos;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(SOS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+struct Seg {
+  std::vector<BlockDesc> blocks;
+  std::vector<int32_t> bfirst;
+  BlockDesc* d_blocks = nullptr;
+  int32_t* d_bfirst = nullptr;
+  SegLaunch L{};
+};
+
+}  // namespace
+
+struct sos_ctx {
+  sos_mesh mesh{};
+  sos_opts opts{};
+  int fp32 = 0;
+  Geom geo{};
+  std::vector<SubDesc> subs;
+  std::vector<FaceDesc> faces;
+  std::vector<int32_t> pairs;
+  std::vector<int32_t> order;
+  int64_t n_local = 0, n_lam = 0, n_nodes = 0;
+  int max_n = 0, max_face = 0;
+  Dev dev{};
+  SubDesc* d_subs = nullptr;
+  FaceDesc* d_faces = nullptr;
+  int32_t* d_pairs = nullptr;
+  int32_t* d_order = nullptr;
+  Seg seg;
+  // workspaces
+  double *u = nullptr, *f = nullptr, *lam = nullptr, *ut = nullptr, *rho = nullptr;
+  void *r = nullptr, *x = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+  double* part = nullptr;       // 3 per segmented block
+  double* part_norm = nullptr;  // 2 per assemble block
+  int n_norm_blocks = 0;
+  double* d_res = nullptr;      // [res, r'r, f'f]
+  CgScal* scal = nullptr;
+  int32_t* ndone = nullptr;
+  unsigned long long* counters = nullptr;  // [0] inner iterations, [1] algorithmic bytes
+  double* h_res = nullptr;                 // pinned, coherent, device-mapped
+  double* d_hres = nullptr;                // device view of h_res
+  int32_t* h_ndone = nullptr;              // pinned
+  unsigned long long* h_counters = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // fused kernel launch shape
+  int fused_threads = 0, fused_cpt = 1;
+  size_t fused_lds = 0;
+  size_t lds_limit = 0;
+  // graph of (check_every outer iterations + check)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_k = 0;
+  std::vector<hipEvent_t> gevents;
+  // timing
+  double kernel_ms = 0.0;
+  int64_t kernel_launches = 0;
+  bool have_load = false;
+};
+
+namespace {
+
+int64_t align64(int64_t v) { return (v + 63) & ~int64_t(63); }
+
+constexpr int kStallOuter = 2000;  // outer iterations without 1% progress
+
+void release(sos_ctx* c) {
+  if (!c) return;
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  for (auto e : c->gevents) hipEventDestroy(e);
+  void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f,
+                  c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->part, c->part_norm, c->d_res,
+                  c->scal, c->ndone, c->counters};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (c->h_res) hipHostFree(c->h_res);
+  if (c->h_ndone) hipHostFree(c->h_ndone);
+  if (c->h_counters) hipHostFree(c->h_counters);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+void invalidate_graph(sos_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_k = 0;
+  for (auto e : c->gevents) hipEventDestroy(e);
+  c->gevents.clear();
+}
+
+int check_opts(const sos_opts* o) {
+  if (o->precision != SOS_FP64 && o->precision != SOS_FP32_INNER) return fail(SOS_EINVAL, "opts.precision must be SOS_FP64 or SOS_FP32_INNER");
+  if (o->mode != SOS_STEPWISE && o->mode != SOS_BATCHED) return fail(SOS_EINVAL, "opts.mode must be SOS_STEPWISE or SOS_BATCHED");
+  if (o->max_outer < 1) return fail(SOS_EINVAL, "opts.max_outer must be >= 1");
+  if (o->max_inner < 1) return fail(SOS_EINVAL, "opts.max_inner must be >= 1");
+  if (o->check_every < 1) return fail(SOS_EINVAL, "opts.check_every must be >= 1");
+  if (!(o->inner_tol >= 0.0) || !(o->inner_abs >= 0.0) || (o->inner_tol == 0.0 && o->inner_abs == 0.0))
+    return fail(SOS_EINVAL, "opts.inner_tol/inner_abs must be >= 0 and not both 0");
+  if (!(o->G > 0.0) || !std::isfinite(o->G)) return fail(SOS_EINVAL, "opts.G must be positive");
+  if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64))
+    return fail(SOS_EINVAL, "opts.block must be 0 or a multiple of 64 in [64, 1024]");
+  return SOS_OK;
+}
+
+int apply_robin(sos_ctx* c, const sos_robin* rb) {
+  if (!rb) return fail(SOS_EINVAL, "robin is NULL");
+  if (rb->order != 0) return fail(SOS_EINVAL, "robin.order: only the zeroth-order operator p is supported");
+  std::vector<double> pv(c->faces.size());
+  for (size_t f = 0; f < c->faces.size(); ++f) {
+    double p = rb->p ? rb->p[f] : rb->p0;
+    if (!(p > 0.0) || !std::isfinite(p)) return fail(SOS_EINVAL, "Robin coefficient of face %zu must be > 0", f);
+    pv[f] = p;
+  }
+  for (size_t f = 0; f < c->faces.size(); ++f) c->faces[f].p = pv[f];
+  for (auto& s : c->subs) {
+    for (int a = 0; a < 3; ++a) {
+      s.elo[a] = s.face[2 * a] >= 0 ? c->faces[s.face[2 * a]].p : 0.0;
+      s.ehi[a] = s.face[2 * a + 1] >= 0 ? c->faces[s.face[2 * a + 1]].p : 0.0;
+    }
+  }
+  return SOS_OK;
+}
+
+// Segmented launch: each subdomain's z-range split into chunks so that the
+// grid has several blocks per compute unit.
+int build_seg(sos_ctx* c) {
+  Seg& g = c->seg;
+  int smax = 0;
+  for (auto& s : c->subs) smax = std::max(smax, s.n[0] * s.n[1]);
+  int cpt = 1;
+  while (cpt < 4 && (smax + cpt - 1) / cpt > 1024) cpt *= 2;
+  if ((smax + cpt - 1) / cpt > 1024) return fail(SOS_EINVAL, "x-y plane of %d nodes exceeds the supported maximum", smax);
+  int threads = ((smax + cpt - 1) / cpt + 63) / 64 * 64;
+  const int n_sub = (int)c->subs.size();
+  const int want = std::max(1, (2 * 256 + n_sub - 1) / n_sub);
+  g.blocks.clear();
+  g.bfirst.assign(1, 0);
+  size_t lds64 = 0, lds32 = 0;
+  for (int s = 0; s < n_sub; ++s) {
+    const SubDesc& d = c->subs[s];
+    const int nz = d.n[2];
+    int chunks = std::min(want, std::max(1, nz / kMinSeg));
+    int len = (nz + chunks - 1) / chunks;
+    for (int z = 0; z < nz; z += len) {
+      BlockDesc b{s, z, std::min(nz, z + len), 0};
+      g.blocks.push_back(b);
+      lds64 = std::max(lds64, march_lds_bytes(d.n[0], d.n[1], b.z1 - b.z0, threads, cpt, 8));
+      lds32 = std::max(lds32, march_lds_bytes(d.n[0], d.n[1], b.z1 - b.z0, threads, cpt, 4));
+    }
+    g.bfirst.push_back((int32_t)g.blocks.size());
+  }
+  if (lds64 > c->lds_limit) return fail(SOS_EINVAL, "subdomain plane needs %zu bytes of LDS (limit %zu)", lds64, c->lds_limit);
+  g.L.nblocks = (int32_t)g.blocks.size();
+  g.L.threads = threads;
+  g.L.cpt = cpt;
+  g.L.lds64 = lds64;
+  g.L.lds32 = lds32;
+  return SOS_OK;
+}
+
+int fused_shape(sos_ctx* c, int threads) {
+  int smax = 0;
+  for (auto& s : c->subs) smax = std::max(smax, s.n[0] * s.n[1]);
+  if (threads == 0) {
+    int cpt = 1;
+    while (cpt < 4 && (smax + cpt - 1) / cpt > 1024) cpt *= 2;
+    threads = ((smax + cpt - 1) / cpt + 63) / 64 * 64;
+    threads = std::max(threads, 256);
+  }
+  int cpt = 1;
+  while (cpt < 4 && cpt * threads < smax) cpt *= 2;
+  if (cpt * threads < smax) return fail(SOS_EINVAL, "block of %d threads cannot cover a %d-node plane", threads, smax);
+  size_t es = c->fp32 ? 4 : 8, lds = 0;
+  for (auto& s : c->subs) lds = std::max(lds, march_lds_bytes(s.n[0], s.n[1], s.n[2], threads, cpt, es));
+  if (lds > c->lds_limit) return fail(SOS_EINVAL, "fused kernel needs %zu bytes of LDS (limit %zu)", lds, c->lds_limit);
+  c->fused_threads = threads;
+  c->fused_cpt = cpt;
+  c->fused_lds = lds;
+  return SOS_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(SOS_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+  return SOS_OK;
+}
+
+int dalloc_v(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) return fail(SOS_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  return SOS_OK;
+}
+
+// ------------------------------------------------------------------ outer iteration pieces
+
+int enqueue_check(sos_ctx* c, double* phi) {
+  hipStream_t st = c->stream;
+  HIPCHK(launch_glue(c->dev, c->max_n, c->u, c->ut, st));
+  HIPCHK(launch_local_residual(c->dev, c->seg.L, c->ut, c->f, c->rho, st));
+  HIPCHK(launch_assemble_norm(c->dev, c->max_n, c->rho, c->f, c->ut, phi, c->part_norm, st));
+  HIPCHK(launch_final_norm(c->part_norm, c->n_norm_blocks, c->d_res, c->d_hres, st));
+  return SOS_OK;
+}
+
+FusedArgs fused_args(sos_ctx* c) {
+  FusedArgs a;
+  a.order = c->d_order;
+  a.res_part = c->part;
+  a.tol_rel = c->opts.inner_tol;
+  a.tol_abs = c->opts.inner_abs;
+  a.max_inner = c->opts.max_inner;
+  a.r = c->r;
+  a.x = c->x;
+  a.p0 = c->p0;
+  a.p1 = c->p1;
+  a.q = c->q;
+  a.u = c->u;
+  a.scal = c->scal;
+  a.iters_total = c->counters;
+  return a;
+}
+
+// One outer iteration in the batched form; ev (optional) brackets the fused kernel.
+int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
+  hipStream_t st = c->stream;
+  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part, st));
+  if (ev0) HIPCHK(hipEventRecord(ev0, st));
+  HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
+  if (ev1) HIPCHK(hipEventRecord(ev1, st));
+  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face, c->u, c->lam, st));
+  return SOS_OK;
+}
+
+// One outer iteration in the stepwise form (host-driven CG steps).
+int stepwise_iteration(sos_ctx* c) {
+  hipStream_t st = c->stream;
+  const SegLaunch& L = c->seg.L;
+  HIPCHK(launch_residual(c->dev, L, c->fp32, c->u, c->f, c->lam, c->r, c->part, st));
+  HIPCHK(launch_cg_init(c->dev, L, c->part, c->opts.inner_tol, c->opts.inner_abs, c->scal, c->ndone, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->opts.timing) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+  }
+  const int n_sub = (int)c->subs.size();
+  int launches = 0;
+  for (int t = 0; t <= c->opts.max_inner; ++t) {
+    void* pold = (t & 1) ? c->p1 : c->p0;
+    void* pnew = (t & 1) ? c->p0 : c->p1;
+    HIPCHK(launch_cg_apply(c->dev, L, c->fp32, t, c->opts.max_inner, c->r, pold, pnew, c->q, c->part, c->scal,
+                           c->ndone, c->counters, st));
+    ++launches;
+    if (t == c->opts.max_inner) break;
+    HIPCHK(launch_cg_update(c->dev, L, c->fp32, t, c->x, pnew, c->r, c->q, c->part, c->scal, c->ndone, st));
+    ++launches;
+    if ((t & 7) == 7) {
+      HIPCHK(hipMemcpyAsync(c->h_ndone, c->ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (*c->h_ndone >= n_sub) break;
+    }
+  }
+  if (c->opts.timing) {
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    c->kernel_ms += ms;
+    c->kernel_launches += launches;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  HIPCHK(launch_add_correction(c->dev, L, c->fp32, c->u, c->x, c->scal, st));
+  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face, c->u, c->lam, st));
+  return SOS_OK;
+}
+
+int build_graph(sos_ctx* c, int k) {
+  invalidate_graph(c);
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = SOS_OK;
+  for (int i = 0; i < k && rc == SOS_OK; ++i)
+    rc = enqueue_batched_iteration(c, nullptr, nullptr);
+  if (rc == SOS_OK) rc = enqueue_check(c, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc != SOS_OK) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SOS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  c->graph = g;
+  HIPCHK(hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+  c->graph_k = k;
+  return SOS_OK;
+}
+
+// Runs outer iterations until the residual <= tol (tol <= 0: exactly max_outer
+// iterations with one final check). Fills stats.
+int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* converged) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = c->stream;
+  *c->h_counters = 0;
+  HIPCHK(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), st));  // never inside a graph
+  c->kernel_ms = 0.0;
+  c->kernel_launches = 0;
+  const bool batched = c->opts.mode == SOS_BATCHED;
+  // HIP events recorded inside a graph cannot be read back with
+  // hipEventElapsedTime: timed runs launch eagerly
+  const bool graph = batched && c->opts.use_graph && !c->opts.timing;
+  const int every = c->opts.check_every;
+  int done = 0, checks = 0;
+  double res = INFINITY, best = INFINITY;
+  int best_at = 0;
+  *converged = false;
+  std::vector<hipEvent_t> evs;
+  while (done < max_outer) {
+    int k = std::min(every, max_outer - done);
+    if (graph) {
+      if (c->graph_k != k) {
+        int rc = build_graph(c, k);
+        if (rc) return rc;
+      }
+      HIPCHK(hipGraphLaunch(c->gexec, st));
+    } else {
+      for (int i = 0; i < k; ++i) {
+        if (batched) {
+          hipEvent_t e0 = nullptr, e1 = nullptr;
+          if (c->opts.timing) {
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            evs.push_back(e0);
+            evs.push_back(e1);
+          }
+          int rc = enqueue_batched_iteration(c, e0, e1);
+          if (rc) return rc;
+        } else {
+          int rc = stepwise_iteration(c);
+          if (rc) return rc;
+        }
+      }
+      int rc = enqueue_check(c, nullptr);
+      if (rc) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (c->opts.timing) {
+      std::vector<hipEvent_t>& E = evs;
+      for (size_t i = 0; i + 1 < E.size(); i += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, E[i], E[i + 1]));
+        c->kernel_ms += ms;
+        c->kernel_launches += 1;
+      }
+      for (auto e : evs) hipEventDestroy(e);
+      evs.clear();
+    }
+    done += k;
+    ++checks;
+    res = *c->h_res;
+    if (!std::isfinite(res)) break;
+    if (tol > 0.0 && res <= tol) {
+      *converged = true;
+      break;
+    }
+    // stagnation: no 1% improvement of the best residual for kStallOuter
+    // outer iterations (e.g. an outer target below the inner solves' floor)
+    if (res < 0.99 * best) {
+      best = res;
+      best_at = done;
+    } else if (tol > 0.0 && done - best_at >= kStallOuter) {
+      break;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->h_counters, c->counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->outer_iters = done;
+    stats->checks = checks;
+    stats->inner_iters = (int64_t)c->h_counters[0];
+    stats->rel_residual = res;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->kernel_ms = c->kernel_ms;
+    stats->kernel_launches = c->kernel_launches;
+    stats->kernel_bytes = (double)c->h_counters[1];
+    stats->block = c->fused_threads;
+  }
+  if (!std::isfinite(res)) return fail(SOS_EBREAKDOWN, "non-finite global residual");
+  return SOS_OK;
+}
+
+int write_phi(sos_ctx* c, double* phi) {
+  HIPCHK(launch_fill(phi, c->n_nodes, 0.0, c->stream));
+  int rc = enqueue_check(c, phi);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SOS_OK;
+}
+
+int reset_state(sos_ctx* c) {
+  HIPCHK(launch_fill(c->u, c->n_local, 0.0, c->stream));
+  HIPCHK(launch_fill(c->lam, c->n_lam, 0.0, c->stream));
+  return SOS_OK;
+}
+
+int solve_common(sos_ctx* c, double tol, double* phi, sos_stats* stats) {
+  if (!(tol > 0.0)) return fail(SOS_EINVAL, "tol must be > 0");
+  if (!phi) return fail(SOS_EINVAL, "phi_nodes is NULL");
+  int rc = reset_state(c);
+  if (rc) return rc;
+  bool conv = false;
+  rc = run_outer(c, tol, c->opts.max_outer, stats, &conv);
+  if (rc) return rc;
+  rc = write_phi(c, phi);
+  if (rc) return rc;
+  if (!conv)
+    return fail(SOS_ENOCONV, "no convergence to %g after %d outer iterations (residual %g%s)", tol,
+                stats ? stats->outer_iters : c->opts.max_outer, *c->h_res,
+                (stats && stats->outer_iters < c->opts.max_outer) ? ", stagnated" : "");
+  return SOS_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C-ABI
+
+extern "C" {
+
+const char* sos_last_error(void) { return g_err.c_str(); }
+
+int sos_opts_default(sos_opts* o, int32_t precision) {
+  if (!o) return fail(SOS_EINVAL, "opts is NULL");
+  std::memset(o, 0, sizeof *o);
+  o->precision = precision;
+  o->mode = precision == SOS_FP32_INNER ? SOS_BATCHED : SOS_STEPWISE;
+  o->max_outer = 100000;
+  o->max_inner = 500;
+  o->check_every = 1;
+  o->use_graph = 1;
+  o->inner_tol = precision == SOS_FP32_INNER ? 1e-2 : 0.0;
+  o->inner_abs = precision == SOS_FP32_INNER ? 0.0 : 1e-10;
+  o->G = 6.672e-11;
+  o->stream = nullptr;
+  o->block = 0;
+  o->timing = 0;
+  return SOS_OK;
+}
+
+int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* robin, const sos_opts* opts,
+              sos_ctx** out) {
+  if (!out) return fail(SOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !part || !robin || !opts) return fail(SOS_EINVAL, "NULL argument");
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  bool any_dir = false;
+  for (int a = 0; a < 3; ++a) {
+    if (mesh->ne[a] < 1) return fail(SOS_EINVAL, "mesh.ne[%d] must be >= 1", a);
+    if (!(mesh->len[a] > 0.0) || !std::isfinite(mesh->len[a])) return fail(SOS_EINVAL, "mesh.len[%d] must be > 0", a);
+  }
+  for (int f = 0; f < 6; ++f) {
+    if (mesh->bc[f] != SOS_DIRICHLET && mesh->bc[f] != SOS_NEUMANN) return fail(SOS_EINVAL, "mesh.bc[%d] invalid", f);
+    any_dir |= mesh->bc[f] == SOS_DIRICHLET;
+  }
+  if (!any_dir) return fail(SOS_EINVAL, "at least one outer face must be Dirichlet (pure Neumann is singular)");
+  std::vector<int32_t> bounds[3];
+  for (int a = 0; a < 3; ++a) {
+    const int np = part->nparts[a], ne = mesh->ne[a];
+    if (np < 1 || np > ne) return fail(SOS_EINVAL, "partition.nparts[%d] must be in [1, ne]", a);
+    bounds[a].push_back(0);
+    if (part->cuts[a]) {
+      for (int k = 0; k < np - 1; ++k) {
+        int v = part->cuts[a][k];
+        if (v <= bounds[a].back() || v >= ne) return fail(SOS_EINVAL, "partition.cuts[%d] must increase strictly inside (0, ne)", a);
+        bounds[a].push_back(v);
+      }
+    } else {
+      if (ne % np) return fail(SOS_EINVAL, "equal split: nparts[%d] must divide ne[%d]", a, a);
+      for (int k = 1; k < np; ++k) bounds[a].push_back(k * (ne / np));
+    }
+    bounds[a].push_back(ne);
+  }
+  sos_ctx* c = new (std::nothrow) sos_ctx();
+  if (!c) return fail(SOS_ENOMEM, "host allocation failed");
+  c->mesh = *mesh;
+  c->opts = *opts;
+  c->fp32 = opts->precision == SOS_FP32_INNER;
+  Geom& g = c->geo;
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = mesh->ne[a];
+    g.nn[a] = 2 * mesh->ne[a] + 1;
+    g.h[a] = mesh->len[a] / mesh->ne[a];
+    g.ks[a] = 1.0 / (3.0 * g.h[a]);
+    g.ms[a] = g.h[a] / 30.0;
+    g.nparts[a] = part->nparts[a];
+  }
+  for (int f = 0; f < 6; ++f) g.bc[f] = mesh->bc[f];
+  g.n_sub = part->nparts[0] * part->nparts[1] * part->nparts[2];
+  c->n_nodes = (int64_t)g.nn[0] * g.nn[1] * g.nn[2];
+  // subdomains
+  const int Px = g.nparts[0], Py = g.nparts[1], Pz = g.nparts[2];
+  int64_t off = 0;
+  c->subs.resize(g.n_sub);
+  for (int pz = 0; pz < Pz; ++pz)
+    for (int py = 0; py < Py; ++py)
+      for (int px = 0; px < Px; ++px) {
+        const int s = px + Px * (py + Py * pz);
+        SubDesc& d = c->subs[s];
+        const int pp[3] = {px, py, pz};
+        int64_t n = 1;
+        for (int a = 0; a < 3; ++a) {
+          const int e0 = bounds[a][pp[a]], e1 = bounds[a][pp[a] + 1];
+          int klo = 0, khi = 2 * (e1 - e0);
+          if (e0 == 0 && mesh->bc[2 * a] == SOS_DIRICHLET) klo = 1;
+          if (e1 == mesh->ne[a] && mesh->bc[2 * a + 1] == SOS_DIRICHLET) khi -= 1;
+          d.n[a] = khi - klo + 1;
+          d.klo[a] = klo;
+          d.ne2[a] = 2 * (e1 - e0);
+          d.lo[a] = 2 * e0 + klo;
+          d.pidx[a] = pp[a];
+          d.e0[a] = e0;
+          d.elo[a] = d.ehi[a] = 0.0;
+          n *= d.n[a];
+        }
+        for (int k = 0; k < 6; ++k) d.face[k] = -1;
+        d.off = off;
+        off = align64(off + n);
+        c->max_n = std::max<int>(c->max_n, (int)n);
+      }
+  c->n_local = off;
+  // directed faces: by s, axis, side
+  int64_t loff = 0;
+  for (int s = 0; s < g.n_sub; ++s) {
+    SubDesc& d = c->subs[s];
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        int q[3] = {d.pidx[0], d.pidx[1], d.pidx[2]};
+        q[a] += side ? 1 : -1;
+        if (q[a] < 0 || q[a] >= g.nparts[a]) continue;
+        FaceDesc F{};
+        F.s = s;
+        F.j = q[0] + Px * (q[1] + Py * q[2]);
+        F.axis = a;
+        F.side = side;
+        const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
+        F.na = d.n[ta];
+        F.nb = d.n[tb];
+        F.lam_off = loff;
+        F.opp = -1;
+        loff += (int64_t)F.na * F.nb;
+        c->max_face = std::max(c->max_face, F.na * F.nb);
+        d.face[2 * a + side] = (int32_t)c->faces.size();
+        c->faces.push_back(F);
+      }
+  }
+  c->n_lam = loff;
+  for (auto& F : c->faces) {
+    const SubDesc& dj = c->subs[F.j];
+    F.opp = dj.face[2 * F.axis + (1 - F.side)];
+    if (F.s < F.j) c->pairs.push_back((int32_t)(&F - &c->faces[0]));
+  }
+  rc = apply_robin(c, robin);
+  if (rc) {
+    release(c);
+    return rc;
+  }
+  // device and launch limits
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    release(c);
+    return fail(SOS_ESTATE, "no usable HIP device");
+  }
+  c->lds_limit = prop.sharedMemPerBlock;
+  if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block))) {
+    release(c);
+    return rc;
+  }
+  // fused order: largest first
+  c->order.resize(g.n_sub);
+  for (int s = 0; s < g.n_sub; ++s) c->order[s] = s;
+  std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) {
+    const SubDesc &A = c->subs[a], &B = c->subs[b];
+    return (int64_t)A.n[0] * A.n[1] * A.n[2] > (int64_t)B.n[0] * B.n[1] * B.n[2];
+  });
+  // allocations
+  const size_t es = c->fp32 ? 4 : 8;
+  Dev tmp{nullptr, nullptr, g, 0};
+  c->n_norm_blocks = assemble_blocks(tmp, c->max_n);
+  if ((rc = dalloc(&c->d_subs, c->subs.size())) || (rc = dalloc(&c->d_faces, c->faces.size())) ||
+      (rc = dalloc(&c->d_pairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||
+      (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
+      (rc = dalloc(&c->u, c->n_local)) || (rc = dalloc(&c->f, c->n_local)) || (rc = dalloc(&c->lam, c->n_lam)) ||
+      (rc = dalloc(&c->ut, c->n_local)) || (rc = dalloc(&c->rho, c->n_local)) ||
+      (rc = dalloc_v(&c->r, c->n_local * es)) || (rc = dalloc_v(&c->x, c->n_local * es)) ||
+      (rc = dalloc_v(&c->p0, c->n_local * es)) || (rc = dalloc_v(&c->p1, c->n_local * es)) ||
+      (rc = dalloc_v(&c->q, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
+      (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4)) ||
+      (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2))) {
+    release(c);
+    return rc;
+  }
+  if (hipHostMalloc((void**)&c->h_res, sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->d_hres, c->h_res, 0) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ndone, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_counters, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+    release(c);
+    return fail(SOS_ENOMEM, "hipHostMalloc failed");
+  }
+  *c->h_res = INFINITY;
+  if (opts->stream) {
+    c->stream = (hipStream_t)opts->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      release(c);
+      return fail(SOS_EHIP, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  c->seg.L.blocks = c->seg.d_blocks;
+  c->seg.L.bfirst = c->seg.d_bfirst;
+  c->dev.subs = c->d_subs;
+  c->dev.faces = c->d_faces;
+  c->dev.geo = g;
+  c->dev.n_faces = (int32_t)c->faces.size();
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !c->faces.empty())
+    e = hipMemcpy(c->d_faces, c->faces.data(), c->faces.size() * sizeof(FaceDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !c->pairs.empty())
+    e = hipMemcpy(c->d_pairs, c->pairs.data(), c->pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_order, c->order.data(), c->order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->seg.d_blocks, c->seg.blocks.data(), c->seg.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->seg.d_bfirst, c->seg.bfirst.data(), c->seg.bfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->f, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->u, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->lam, 0, std::max<int64_t>(1, c->n_lam) * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->ut, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->rho, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    release(c);
+    return fail(SOS_EHIP, "setup copies: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return SOS_OK;
+}
+
+int sos_set_robin(sos_ctx* c, const sos_robin* robin) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  int rc = apply_robin(c, robin);
+  if (rc) return rc;
+  invalidate_graph(c);
+  hipError_t e = hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !c->faces.empty())
+    e = hipMemcpy(c->d_faces, c->faces.data(), c->faces.size() * sizeof(FaceDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(SOS_EHIP, "set_robin copies: %s", hipGetErrorString(e));
+  return SOS_OK;
+}
+
+int sos_set_opts(sos_ctx* c, const sos_opts* o) {
+  if (!c || !o) return fail(SOS_EINVAL, "NULL argument");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if ((o->precision == SOS_FP32_INNER) != (c->fp32 != 0)) return fail(SOS_EINVAL, "precision is fixed at setup");
+  if (o->stream && o->stream != c->stream) return fail(SOS_EINVAL, "the stream is fixed at setup");
+  const int old_block = c->opts.block;
+  void* st = c->opts.stream;
+  c->opts = *o;
+  c->opts.stream = st;
+  if (o->block != old_block) {
+    rc = fused_shape(c, o->block);
+    if (rc) return rc;
+  }
+  invalidate_graph(c);
+  return SOS_OK;
+}
+
+int sos_faces(const sos_ctx* c, int32_t* n, int32_t* sjas) {
+  if (!c || !n) return fail(SOS_EINVAL, "NULL argument");
+  *n = (int32_t)c->faces.size();
+  if (sjas)
+    for (size_t f = 0; f < c->faces.size(); ++f) {
+      sjas[4 * f] = c->faces[f].s;
+      sjas[4 * f + 1] = c->faces[f].j;
+      sjas[4 * f + 2] = c->faces[f].axis;
+      sjas[4 * f + 3] = c->faces[f].side;
+    }
+  return SOS_OK;
+}
+
+int sos_layout(const sos_ctx* c, int32_t* n_sub, int64_t* offsets, int32_t* dims, int32_t* lo, int64_t* face_off) {
+  if (!c || !n_sub) return fail(SOS_EINVAL, "NULL argument");
+  *n_sub = (int32_t)c->subs.size();
+  for (size_t s = 0; s < c->subs.size(); ++s) {
+    if (offsets) offsets[s] = c->subs[s].off;
+    for (int a = 0; a < 3; ++a) {
+      if (dims) dims[3 * s + a] = c->subs[s].n[a];
+      if (lo) lo[3 * s + a] = c->subs[s].lo[a];
+    }
+  }
+  if (offsets) offsets[c->subs.size()] = c->n_local;
+  if (face_off) {
+    for (size_t f = 0; f < c->faces.size(); ++f) face_off[f] = c->faces[f].lam_off;
+    face_off[c->faces.size()] = c->n_lam;
+  }
+  return SOS_OK;
+}
+
+int sos_set_density(sos_ctx* c, const double* drho) {
+  if (!c || !drho) return fail(SOS_EINVAL, "NULL argument");
+  HIPCHK(launch_load_density(c->dev, c->max_n, drho, c->opts.G, c->f, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->have_load = true;
+  return SOS_OK;
+}
+
+int sos_solve(sos_ctx* c, const double* drho, double tol, double* phi, sos_stats* stats) {
+  if (!c || !drho) return fail(SOS_EINVAL, "NULL argument");
+  HIPCHK(launch_load_density(c->dev, c->max_n, drho, c->opts.G, c->f, c->stream));
+  c->have_load = true;
+  return solve_common(c, tol, phi, stats);
+}
+
+int sos_solve_load(sos_ctx* c, const double* fn, double tol, double* phi, sos_stats* stats) {
+  if (!c || !fn) return fail(SOS_EINVAL, "NULL argument");
+  HIPCHK(launch_load_nodes(c->dev, c->max_n, fn, c->f, c->stream));
+  c->have_load = true;
+  return solve_common(c, tol, phi, stats);
+}
+
+int sos_iterate(sos_ctx* c, int32_t n, sos_stats* stats) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  if (n < 1) return fail(SOS_EINVAL, "n must be >= 1");
+  if (!c->have_load) return fail(SOS_ESTATE, "no load set (sos_set_density or a solve first)");
+  bool conv = false;
+  return run_outer(c, 0.0, n, stats, &conv);
+}
+
+int sos_residual(sos_ctx* c, double* phi, double* res) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  int rc = phi ? write_phi(c, phi) : enqueue_check(c, nullptr);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (res) *res = *c->h_res;
+  return SOS_OK;
+}
+
+int sos_get_state(sos_ctx* c, double* u, double* lam) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  if (u) HIPCHK(hipMemcpyAsync(u, c->u, c->n_local * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (lam && c->n_lam) HIPCHK(hipMemcpyAsync(lam, c->lam, c->n_lam * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SOS_OK;
+}
+
+int sos_set_state(sos_ctx* c, const double* u, const double* lam) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  if (u) HIPCHK(hipMemcpyAsync(c->u, u, c->n_local * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (lam && c->n_lam) HIPCHK(hipMemcpyAsync(c->lam, lam, c->n_lam * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SOS_OK;
+}
+
+int sos_apply_local(sos_ctx* c, int32_t precision, const void* x, void* y) {
+  if (!c || !x || !y) return fail(SOS_EINVAL, "NULL argument");
+  if (precision != SOS_FP64 && precision != SOS_FP32_INNER) return fail(SOS_EINVAL, "precision invalid");
+  SegLaunch L = c->seg.L;
+  if (precision == SOS_FP32_INNER && L.lds32 > c->lds_limit) return fail(SOS_EINVAL, "LDS limit");
+  HIPCHK(launch_apply(c->dev, L, precision == SOS_FP32_INNER, x, y, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SOS_OK;
+}
+
+void sos_destroy(sos_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  release(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Host-side launch wrappers of the HIP kernels (defined in sos_kernels.hip).
+#pragma once
+
+#include "sos_internal.h"
+
+namespace sos {
+
+// A block of a segmented launch: subdomain s, z-range [z0, z1) of its planes.
+struct BlockDesc {
+  int32_t s, z0, z1, pad;
+};
+
+// Launch geometry of a segmented launch (one block per BlockDesc).
+struct SegLaunch {
+  const BlockDesc* blocks;  // device
+  const int32_t* bfirst;    // device, n_sub+1: blocks of s are [bfirst[s], bfirst[s+1])
+  int32_t nblocks;
+  int32_t threads;          // threads per block (multiple of 64)
+  int32_t cpt;              // x-y columns per thread (1, 2 or 4)
+  size_t lds64;             // dynamic LDS bytes for FP64 marches
+  size_t lds32;             // dynamic LDS bytes for FP32 marches
+};
+
+struct Dev {
+  const SubDesc* subs;      // device descriptors
+  const FaceDesc* faces;
+  Geom geo;
+  int32_t n_faces;
+};
+
+constexpr int kMinSeg = 8;  // shortest z-segment of a march (planes)
+
+// Number of z-segments a block of `threads` threads with `cpt` x-y columns per
+// thread marches at once over a z-range of zlen planes of an nx*ny plane.
+__host__ __device__ inline int march_segments(int nx, int ny, int zlen, int threads, int cpt) {
+  int S = nx * ny;
+  int g = (threads * cpt) / S;
+  int gz = (zlen + kMinSeg - 1) / kMinSeg;
+  if (g > gz) g = gz;
+  return g < 1 ? 1 : g;
+}
+// LDS bytes of such a march: three zero-padded planes per segment.
+__host__ __device__ inline size_t march_lds_bytes(int nx, int ny, int zlen, int threads, int cpt,
+                                                  size_t elem) {
+  size_t sp = (size_t)(nx + 2 * kPad) * (size_t)(ny + 2 * kPad);
+  return 3 * sp * (size_t)march_segments(nx, ny, zlen, threads, cpt) * elem;
+}
+
+// f_s from a per-element density (FP64), for all subdomains.
+hipError_t launch_load_density(const Dev& d, int max_n, const double* drho, double G,
+                               double* f_loc, hipStream_t st);
+// f_s = f_nodes / multiplicity.
+hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, double* f_loc,
+                             hipStream_t st);
+// r = f + sum R^T lambda - A u (FP64 apply), stored as Tr; partials rz, rr, bb per block.
+hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u,
+                           const double* f, const double* lam, void* r_out, double* part,
+                           hipStream_t st);
+// Per-subdomain CG scalars from the residual partials (stepwise path).
+hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel,
+                          double tol_abs, CgScal* scal, int32_t* ndone, hipStream_t st);
+// Stepwise CG, iteration t: p <- D^-1 r + beta p ; q = A p ; partial p'q.
+hipError_t launch_cg_apply(const Dev& d, const SegLaunch& L, int fp32, int t, int max_inner,
+                           const void* r, const void* p_old, void* p_new, void* q, double* part,
+                           CgScal* scal, int32_t* ndone, unsigned long long* counters, hipStream_t st);
+// Stepwise CG, iteration t: x += alpha p ; r -= alpha q ; partials r'z, r'r.
+hipError_t launch_cg_update(const Dev& d, const SegLaunch& L, int fp32, int t, void* x, const void* p,
+                            void* r, const void* q, double* part, CgScal* scal, int32_t* ndone,
+                            hipStream_t st);
+// u += x for every subdomain whose inner solve took at least one iteration.
+hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, double* u, const void* x,
+                                 const CgScal* scal, hipStream_t st);
+// The fused inner solve: one block per subdomain (order gives the block->subdomain
+// map) runs its whole CG and adds the correction to u.
+struct FusedArgs {
+  const int32_t* order;    // n_sub subdomains, largest first
+  const double* res_part;  // residual partials (segmented launch L)
+  double tol_rel, tol_abs;
+  int32_t max_inner;
+  void *r, *x, *p0, *p1, *q;
+  double* u;
+  CgScal* scal;
+  unsigned long long* iters_total;  // [0] CG iterations, [1] algorithmic bytes
+};
+hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
+                           const FusedArgs& a, hipStream_t st);
+// Robin exchange over all interfaces (in place, both directions).
+hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_face,
+                           const double* u, double* lam, hipStream_t st);
+// Glue: utilde = average of copies (local layout).
+hipError_t launch_glue(const Dev& d, int max_n, const double* u, double* ut, hipStream_t st);
+// rho = f - K^N utilde (FP64, Neumann local stiffness).
+hipError_t launch_local_residual(const Dev& d, const SegLaunch& L, const double* ut, const double* f,
+                                 double* rho, hipStream_t st);
+// Owned nodes: r = sum of rho copies, f = sum of f copies, partial r'r, f'f;
+// phi (if not null) <- utilde on owned nodes.
+hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, const double* f,
+                                const double* ut, double* phi, double* part, hipStream_t st);
+// Number of partials (pairs) written by launch_assemble_norm.
+int assemble_blocks(const Dev& d, int max_n);
+// res = sqrt(sum rr / sum ff) -> dev_out[0], host_out[0] (host-mapped, may be null).
+hipError_t launch_final_norm(const double* part, int32_t nblk, double* dev_out, double* host_out,
+                             hipStream_t st);
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st);
+// y = A x (diagnostic; fp32 selects float vectors).
+hipError_t launch_apply(const Dev& d, const SegLaunch& L, int fp32, const void* x, void* y,
+                        hipStream_t st);
+
+constexpr int kAssembleThreads = 256;
+
+}  // namespace sos

@@ -1,0 +1,1043 @@
+// HIP kernels of the Robin-Schwarz subdomain solves (gfx950, wave64).
+//
+// Operator. On a subdomain box the Robin-augmented Q2 stiffness is the
+// Kronecker sum of 1D factors (tensor-product elements, Sec. 3 operator p on
+// interface ends):
+//   A = Kx' (x) My (x) Mz + Mx (x) Ky' (x) Mz + Mx (x) My (x) Kz',
+// K' = K + diag(p at interface ends). It is applied matrix-free, marching over
+// the z-planes of the subdomain: every x-y plane of the input is staged in a
+// zero-padded LDS plane, reduced along y (u = My p, v = Ky' p) and then along x
+// (S = Kx' u + Mx v, T = Mx u), and each plane's (S, T) is scattered into a
+// ring of five z-accumulators held in registers:
+//   q_k = sum_k' Mz[k][k'] S_k' + Kz'[k][k'] T_k'.
+// About 30 flops per node, no MFMA: the path is bound by memory traffic.
+//
+// 1D rows of the assembled Q2 matrices on an interval of ne elements (closure
+// nodes 0..2ne): stiffness (1/(3h)) x {1,-8,14,-8,1} at interior vertices,
+// {-8,16,-8} at mid-points, {7,-8,1} / {1,-8,7} at the two ends; mass
+// (h/30) x {-1,2,8,2,-1}, {2,16,2}, {4,2,-1}, {-1,2,4}. The +-1 entries are
+// the same in every row, the +-2 entries are those of a vertex row or zero, so
+// only the centre entry depends on the node type. Neighbours outside the
+// subdomain's unknowns read the zero padding of the LDS plane (x, y) or feed
+// outputs outside the subdomain that are never stored (z).
+//
+// CG (Sec. 6: diagonal preconditioner). Each iteration is two passes:
+//   A: p = D^-1 r + beta p_old (recomputed on halo planes), q = A p, p'q
+//   B: x += alpha p, r -= alpha q, r'z, r'r  (pointwise)
+// Reductions are wave64 shuffles, then a fixed-order sum over waves and over
+// the blocks of a subdomain: results are bitwise repeatable.
+#include "sos_kernels.h"
+
+#include <math.h>
+
+namespace sos {
+
+// ---------------------------------------------------------------------------- 1D rows
+
+template <typename T>
+struct Row {
+  T k0, m0, k2, m2;  // centre and +-2 entries (the +-1 entries are -8ks, 2ms)
+};
+
+template <typename T>
+__device__ __forceinline__ Row<T> row_of(int c, int ne2, T ks, T ms, T elo, T ehi) {
+  Row<T> r;
+  if (c & 1) {
+    r.k0 = T(16) * ks;
+    r.m0 = T(16) * ms;
+    r.k2 = T(0);
+    r.m2 = T(0);
+  } else {
+    r.k2 = ks;
+    r.m2 = -ms;
+    if (c == 0) {
+      r.k0 = T(7) * ks + elo;
+      r.m0 = T(4) * ms;
+    } else if (c == ne2) {
+      r.k0 = T(7) * ks + ehi;
+      r.m0 = T(4) * ms;
+    } else {
+      r.k0 = T(14) * ks;
+      r.m0 = T(8) * ms;
+    }
+  }
+  return r;
+}
+
+// 0 mid-point, 1 interior vertex, 2 first closure node, 3 last closure node
+__device__ __forceinline__ int row_kind(int c, int ne2) {
+  return (c & 1) ? 0 : (c == 0 ? 2 : (c == ne2 ? 3 : 1));
+}
+
+// ---------------------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum N values over the block; every thread receives the sums (fixed order).
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
+  __shared__ double red[N * 16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) red[n * 16 + w] = v[n];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += red[n * 16 + k];
+    v[n] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------- march geometry
+
+template <typename T, int CPT>
+struct Slots {
+  int nx, ny, nz, S, PX, SP, G, seglen;
+  int64_t off;
+  int c[CPT], i[CPT], j[CPT], g[CPT], z0[CPT], z1[CPT], lp[CPT];
+  bool act[CPT];
+  T kx0[CPT], mx0[CPT], kx2[CPT], mx2[CPT];
+  T ky0[CPT], my0[CPT], ky2[CPT], my2[CPT];
+  T dv0[CPT], dv1[CPT], dv2[CPT], dv3[CPT];  // inverse diagonal per z row kind
+  T kx1, mx1, ky1, my1, kz1, mz1;
+  int zklo, zne2;
+  T zks, zms, zelo, zehi;
+};
+
+template <typename T, int CPT>
+__device__ __forceinline__ void slots_init(Slots<T, CPT>& sl, const SubDesc& d, const Geom& geo, int zb0,
+                                           int zb1, bool robin) {
+  sl.nx = d.n[0];
+  sl.ny = d.n[1];
+  sl.nz = d.n[2];
+  sl.S = sl.nx * sl.ny;
+  sl.PX = sl.nx + 2 * kPad;
+  sl.SP = sl.PX * (sl.ny + 2 * kPad);
+  sl.off = d.off;
+  const int NT = blockDim.x;
+  const int zlen = zb1 - zb0;
+  sl.G = march_segments(sl.nx, sl.ny, zlen, NT, CPT);
+  sl.seglen = (zlen + sl.G - 1) / sl.G;
+  const T ksx = T(geo.ks[0]), msx = T(geo.ms[0]);
+  const T ksy = T(geo.ks[1]), msy = T(geo.ms[1]);
+  sl.zks = T(geo.ks[2]);
+  sl.zms = T(geo.ms[2]);
+  sl.kx1 = T(-8) * ksx;
+  sl.mx1 = T(2) * msx;
+  sl.ky1 = T(-8) * ksy;
+  sl.my1 = T(2) * msy;
+  sl.kz1 = T(-8) * sl.zks;
+  sl.mz1 = T(2) * sl.zms;
+  sl.zklo = d.klo[2];
+  sl.zne2 = d.ne2[2];
+  sl.zelo = robin ? T(d.elo[2]) : T(0);
+  sl.zehi = robin ? T(d.ehi[2]) : T(0);
+  // centre entries of the four z row kinds (for the diagonal)
+  T kz0[4], mz0[4];
+  kz0[0] = T(16) * sl.zks;
+  mz0[0] = T(16) * sl.zms;
+  kz0[1] = T(14) * sl.zks;
+  mz0[1] = T(8) * sl.zms;
+  kz0[2] = T(7) * sl.zks + sl.zelo;
+  mz0[2] = T(4) * sl.zms;
+  kz0[3] = T(7) * sl.zks + sl.zehi;
+  mz0[3] = T(4) * sl.zms;
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    const int sigma = threadIdx.x + NT * m;
+    const int g = sigma / sl.S;
+    const int col = sigma - g * sl.S;
+    sl.g[m] = g;
+    sl.z0[m] = zb0 + g * sl.seglen;
+    sl.z1[m] = min(zb1, sl.z0[m] + sl.seglen);
+    sl.act[m] = (g < sl.G) && (sl.z0[m] < zb1);
+    sl.c[m] = col;
+    const int i = col % sl.nx, j = col / sl.nx;
+    sl.i[m] = i;
+    sl.j[m] = j;
+    sl.lp[m] = g * 3 * sl.SP + (i + kPad) + sl.PX * (j + kPad);
+    Row<T> rx = row_of<T>(i + d.klo[0], d.ne2[0], ksx, msx, robin ? T(d.elo[0]) : T(0),
+                          robin ? T(d.ehi[0]) : T(0));
+    Row<T> ry = row_of<T>(j + d.klo[1], d.ne2[1], ksy, msy, robin ? T(d.elo[1]) : T(0),
+                          robin ? T(d.ehi[1]) : T(0));
+    sl.kx0[m] = rx.k0;
+    sl.mx0[m] = rx.m0;
+    sl.kx2[m] = rx.k2;
+    sl.mx2[m] = rx.m2;
+    sl.ky0[m] = ry.k0;
+    sl.my0[m] = ry.m0;
+    sl.ky2[m] = ry.k2;
+    sl.my2[m] = ry.m2;
+    const T a1 = rx.k0 * ry.m0 + rx.m0 * ry.k0;
+    const T a2 = rx.m0 * ry.m0;
+    sl.dv0[m] = T(1) / (a1 * mz0[0] + a2 * kz0[0]);
+    sl.dv1[m] = T(1) / (a1 * mz0[1] + a2 * kz0[1]);
+    sl.dv2[m] = T(1) / (a1 * mz0[2] + a2 * kz0[2]);
+    sl.dv3[m] = T(1) / (a1 * mz0[3] + a2 * kz0[3]);
+  }
+}
+
+template <typename T, int CPT>
+__device__ __forceinline__ T slot_dinv(const Slots<T, CPT>& sl, int m, int k) {
+  // blend with 0/1 weights: a select between struct fields would make the
+  // compiler keep the whole slot state in scratch memory
+  const int c = k + sl.zklo;
+  const bool mid = (c & 1) != 0;
+  const T w0 = mid ? T(1) : T(0);
+  const T w2 = (!mid && c == 0) ? T(1) : T(0);
+  const T w3 = (!mid && c == sl.zne2) ? T(1) : T(0);
+  const T w1 = T(1) - w0 - w2 - w3;
+  return w0 * sl.dv0[m] + w1 * sl.dv1[m] + w2 * sl.dv2[m] + w3 * sl.dv3[m];
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_zero(T* lds, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) lds[e] = T(0);
+}
+
+// The z-march. load(idx, own, dinv) returns the operand at global index idx
+// of a plane inside the subdomain (own: the plane belongs to the slot's
+// segment; dinv: inverse diagonal there). store(idx, i, j, k, q, p_k, dinv)
+// receives the finished output at plane k of the slot's own segment, with the
+// operand value p_k at that node.
+template <typename T, int CPT, class LoadF, class StoreF>
+__device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, LoadF& load, StoreF& store) {
+  T acc[CPT][5];
+  T pr[CPT][3];
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[m][q] = T(0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) pr[m][q] = T(0);
+  }
+  const int steps = sl.seglen + 4;
+  const int PX = sl.PX, SP = sl.SP;
+  for (int step = 0; step < steps; ++step) {
+    bool inr[CPT];
+    int kp[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      kp[m] = sl.z0[m] - 2 + step;
+      inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] < sl.nz;
+      T v = T(0);
+      if (inr[m]) {
+        const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * kp[m];
+        const bool own = kp[m] >= sl.z0[m] && kp[m] < sl.z1[m];
+        v = load(idx, own, slot_dinv(sl, m, kp[m]));
+        lds[sl.lp[m]] = v;
+      }
+      pr[m][2] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (inr[m]) {
+        const T* P = lds + sl.lp[m];
+        const T a0 = P[0];
+        const T s1 = P[-PX] + P[PX];
+        const T s2 = P[-2 * PX] + P[2 * PX];
+        const T u = sl.my0[m] * a0 + sl.my1 * s1 + sl.my2[m] * s2;
+        const T v = sl.ky0[m] * a0 + sl.ky1 * s1 + sl.ky2[m] * s2;
+        lds[sl.lp[m] + SP] = u;
+        lds[sl.lp[m] + 2 * SP] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (inr[m]) {
+        const T* U = lds + sl.lp[m] + SP;
+        const T* V = U + SP;
+        const T u0 = U[0], u1 = U[-1] + U[1], u2 = U[-2] + U[2];
+        const T v0 = V[0], v1 = V[-1] + V[1], v2 = V[-2] + V[2];
+        const T Sx = sl.kx0[m] * u0 + sl.kx1 * u1 + sl.kx2[m] * u2 + sl.mx0[m] * v0 + sl.mx1 * v1 +
+                     sl.mx2[m] * v2;
+        const T Tx = sl.mx0[m] * u0 + sl.mx1 * u1 + sl.mx2[m] * u2;
+        const Row<T> rz = row_of<T>(kp[m] + sl.zklo, sl.zne2, sl.zks, sl.zms, sl.zelo, sl.zehi);
+        const T c1 = sl.mz1 * Sx + sl.kz1 * Tx;
+        const T c2 = rz.m2 * Sx + rz.k2 * Tx;
+        acc[m][0] += c2;
+        acc[m][1] += c1;
+        acc[m][2] += rz.m0 * Sx + rz.k0 * Tx;
+        acc[m][3] += c1;
+        acc[m][4] += c2;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (sl.act[m]) {
+        const int k = sl.z0[m] - 4 + step;
+        if (k >= sl.z0[m] && k < sl.z1[m])
+          store(sl.off + sl.c[m] + (int64_t)sl.S * k, sl.i[m], sl.j[m], k, acc[m][0], pr[m][0],
+                slot_dinv(sl, m, k));
+      }
+      acc[m][0] = acc[m][1];
+      acc[m][1] = acc[m][2];
+      acc[m][2] = acc[m][3];
+      acc[m][3] = acc[m][4];
+      acc[m][4] = T(0);
+      pr[m][0] = pr[m][1];
+      pr[m][1] = pr[m][2];
+    }
+  }
+}
+
+// Launch bound per x-y columns per thread (the host never launches more).
+template <int CPT>
+struct Bound {
+  static constexpr int value = CPT == 2 ? 576 : 1024;
+};
+
+// Robin data added to the local right-hand side at node (i, j, k).
+struct LamOff {
+  int64_t o[6];  // lambda offset per (axis, side) face, -1 if none
+};
+
+__device__ __forceinline__ LamOff lam_offsets(const Dev& d, const SubDesc& sd) {
+  LamOff L;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) L.o[f] = sd.face[f] >= 0 ? d.faces[sd.face[f]].lam_off : -1;
+  return L;
+}
+
+__device__ __forceinline__ double lam_terms(const LamOff& L, const double* lam, int i, int j, int k, int nx,
+                                            int ny, int nz) {
+  double a = 0.0;
+  if (i == 0 && L.o[0] >= 0) a += lam[L.o[0] + j + (int64_t)ny * k];
+  if (i == nx - 1 && L.o[1] >= 0) a += lam[L.o[1] + j + (int64_t)ny * k];
+  if (j == 0 && L.o[2] >= 0) a += lam[L.o[2] + i + (int64_t)nx * k];
+  if (j == ny - 1 && L.o[3] >= 0) a += lam[L.o[3] + i + (int64_t)nx * k];
+  if (k == 0 && L.o[4] >= 0) a += lam[L.o[4] + i + (int64_t)nx * j];
+  if (k == nz - 1 && L.o[5] >= 0) a += lam[L.o[5] + i + (int64_t)nx * j];
+  return a;
+}
+
+// Algorithmic bytes of an inner solve of t CG iterations on subdomain sd:
+// per iteration pass A reads r, p_old and writes p, q, pass B reads p, q, x, r
+// and writes x, r (10 vectors; the first iteration reads neither p_old nor x),
+// then the correction u += x reads x and u and writes u (FP64).
+__device__ __forceinline__ unsigned long long cg_bytes(const SubDesc& sd, int t, int es) {
+  if (t <= 0) return 0ull;
+  const unsigned long long n = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
+  return n * ((unsigned long long)(10 * t - 2) * es + es + 16ull);
+}
+
+// ---------------------------------------------------------------------------- outer kernels
+
+// r = f + sum_F R^T lambda_F - A u, rounded to TO; partials (r'D^-1 r, r'r, b'b).
+template <typename TO, int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
+                                                   const double* __restrict__ f, const double* __restrict__ lam,
+                                                   TO* __restrict__ r, double* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* lds = reinterpret_cast<double*>(smem);
+  const BlockDesc bd = blocks[blockIdx.x];
+  const SubDesc sd = d.subs[bd.s];
+  Slots<double, CPT> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
+  const LamOff L = lam_offsets(d, sd);
+  lds_zero(lds, sl.G * 3 * sl.SP);
+  __syncthreads();
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const int nx = sl.nx, ny = sl.ny, nz = sl.nz;
+  auto load = [=](int64_t idx, bool, double) { return u[idx]; };
+  auto store = [&](int64_t idx, int i, int j, int k, double q, double, double dinv) {
+    const double b = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
+    const TO rt = TO(b - q);
+    r[idx] = rt;
+    const double rd = double(rt);
+    a0 += rd * rd * dinv;
+    a1 += rd * rd;
+    a2 += b * b;
+  };
+  zmarch(sl, lds, load, store);
+  double acc[3] = {a0, a1, a2};
+  block_sum(acc);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = acc[0];
+    part[3 * blockIdx.x + 1] = acc[1];
+    part[3 * blockIdx.x + 2] = acc[2];
+  }
+}
+
+// rho = f - K^N ut (Neumann local stiffness: no Robin terms).
+template <int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ ut,
+                                                         const double* __restrict__ f, double* __restrict__ rho) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* lds = reinterpret_cast<double*>(smem);
+  const BlockDesc bd = blocks[blockIdx.x];
+  const SubDesc sd = d.subs[bd.s];
+  Slots<double, CPT> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
+  lds_zero(lds, sl.G * 3 * sl.SP);
+  __syncthreads();
+  auto load = [=](int64_t idx, bool, double) { return ut[idx]; };
+  auto store = [=](int64_t idx, int, int, int, double q, double, double) { rho[idx] = f[idx] - q; };
+  zmarch(sl, lds, load, store);
+}
+
+// y = A x (diagnostic).
+template <typename T, int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockDesc* blocks, const T* __restrict__ x,
+                                                T* __restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const BlockDesc bd = blocks[blockIdx.x];
+  const SubDesc sd = d.subs[bd.s];
+  Slots<T, CPT> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
+  lds_zero(lds, sl.G * 3 * sl.SP);
+  __syncthreads();
+  auto load = [=](int64_t idx, bool, T) { return x[idx]; };
+  auto store = [=](int64_t idx, int, int, int, T q, T, T) { y[idx] = q; };
+  zmarch(sl, lds, load, store);
+}
+
+// ---------------------------------------------------------------------------- stepwise CG
+
+__global__ void k_cg_init(int n_sub, const int32_t* __restrict__ bfirst, const double* __restrict__ part,
+                          double tol_rel, double tol_abs, CgScal* __restrict__ scal, int32_t* ndone) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) *ndone = 0;
+  if (s >= n_sub) return;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int b = bfirst[s]; b < bfirst[s + 1]; ++b) {
+    rz += part[3 * b];
+    rr += part[3 * b + 1];
+    bb += part[3 * b + 2];
+  }
+  CgScal c;
+  c.rz[0] = rz;
+  c.rz[1] = rz;
+  c.rr0 = rr;
+  c.stop2 = fmax(tol_rel * tol_rel * rr, tol_abs * tol_abs * bb);
+  c.done = 0;
+  c.iters = 0;
+  c.breakdown = 0;
+  c.pad = 0;
+  scal[s] = c;
+}
+
+template <typename T, int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
+                                                   int t, int max_inner, const T* __restrict__ r,
+                                                   const T* __restrict__ pold, T* __restrict__ pnew,
+                                                   T* __restrict__ q, double* __restrict__ part,
+                                                   CgScal* __restrict__ scal, int32_t* ndone,
+                                                   unsigned long long* counters) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const BlockDesc bd = blocks[blockIdx.x];
+  const int s = bd.s;
+  if (scal[s].done) return;
+  const int b0 = bfirst[s], b1 = bfirst[s + 1];
+  const bool leader = (blockIdx.x == b0) && (threadIdx.x == 0);
+  double rz, rr;
+  if (t == 0) {
+    rz = scal[s].rz[0];
+    rr = scal[s].rr0;
+  } else {
+    rz = 0.0;
+    rr = 0.0;
+    for (int b = b0; b < b1; ++b) {
+      rz += part[3 * b + 1];
+      rr += part[3 * b + 2];
+    }
+  }
+  const bool bad = !isfinite(rr) || !isfinite(rz);
+  if (bad || !(rr > scal[s].stop2) || t >= max_inner) {
+    if (leader) {
+      scal[s].done = 1;
+      scal[s].iters = t;
+      scal[s].breakdown = bad ? 1 : 0;
+      atomicAdd(ndone, 1);
+      const SubDesc& sd = d.subs[s];
+      atomicAdd(&counters[0], (unsigned long long)t);
+      atomicAdd(&counters[1], cg_bytes(sd, t, sizeof(T)));
+    }
+    return;
+  }
+  const double beta = t == 0 ? 0.0 : rz / scal[s].rz[(t - 1) & 1];
+  if (leader) scal[s].rz[t & 1] = rz;
+  const SubDesc sd = d.subs[s];
+  Slots<T, CPT> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
+  lds_zero(lds, sl.G * 3 * sl.SP);
+  __syncthreads();
+  const T tb = T(beta);
+  const bool first = t == 0;
+  double a0 = 0.0;
+  auto load = [=](int64_t idx, bool own, T dinv) {
+    T pn = dinv * r[idx];
+    if (!first) pn += tb * pold[idx];
+    if (own) pnew[idx] = pn;
+    return pn;
+  };
+  auto store = [&](int64_t idx, int, int, int, T qv, T pk, T) {
+    q[idx] = qv;
+    a0 += double(pk) * double(qv);
+  };
+  zmarch(sl, lds, load, store);
+  double acc[1] = {a0};
+  block_sum(acc);
+  if (threadIdx.x == 0) part[3 * blockIdx.x] = acc[0];
+}
+
+template <typename T, int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_cg_update(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
+                                                    int t, T* __restrict__ x, const T* __restrict__ p,
+                                                    T* __restrict__ r, const T* __restrict__ q,
+                                                    double* __restrict__ part, CgScal* __restrict__ scal,
+                                                    int32_t* ndone) {
+  const BlockDesc bd = blocks[blockIdx.x];
+  const int s = bd.s;
+  if (scal[s].done) return;
+  const int b0 = bfirst[s], b1 = bfirst[s + 1];
+  double pq = 0.0;
+  for (int b = b0; b < b1; ++b) pq += part[3 * b];
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == b0 && threadIdx.x == 0) {
+      scal[s].done = 1;
+      scal[s].iters = t;
+      scal[s].breakdown = 1;
+      atomicAdd(ndone, 1);
+    }
+    return;
+  }
+  const T alpha = T(scal[s].rz[t & 1] / pq);
+  const SubDesc sd = d.subs[s];
+  Slots<T, CPT> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    if (!sl.act[m]) continue;
+    for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
+      const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
+      const T pv = p[idx];
+      x[idx] = t == 0 ? alpha * pv : x[idx] + alpha * pv;
+      const T rv = r[idx] - alpha * q[idx];
+      r[idx] = rv;
+      const double rd = double(rv);
+      acc[0] += rd * rd * double(slot_dinv(sl, m, k));
+      acc[1] += rd * rd;
+    }
+  }
+  block_sum(acc);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 1] = acc[0];
+    part[3 * blockIdx.x + 2] = acc[1];
+  }
+}
+
+template <typename T, int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_add_correction(Dev d, const BlockDesc* blocks, double* __restrict__ u,
+                                                         const T* __restrict__ x, const CgScal* __restrict__ scal) {
+  const BlockDesc bd = blocks[blockIdx.x];
+  if (scal[bd.s].iters <= 0) return;
+  const SubDesc sd = d.subs[bd.s];
+  Slots<T, CPT> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    if (!sl.act[m]) continue;
+    for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
+      const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
+      u[idx] += double(x[idx]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- fused CG
+
+// One block per subdomain: the complete CG solve of A_s d = r_s from d = 0,
+// then u_s += d. No inter-block communication.
+template <typename T, int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int s = a.order[blockIdx.x];
+  const SubDesc sd = d.subs[s];
+  Slots<T, CPT> sl;
+  slots_init(sl, sd, d.geo, 0, sd.n[2], true);
+  T* __restrict__ r = reinterpret_cast<T*>(a.r);
+  T* __restrict__ x = reinterpret_cast<T*>(a.x);
+  T* __restrict__ p0 = reinterpret_cast<T*>(a.p0);
+  T* __restrict__ p1 = reinterpret_cast<T*>(a.p1);
+  T* __restrict__ q = reinterpret_cast<T*>(a.q);
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int b = bfirst[s]; b < bfirst[s + 1]; ++b) {
+    rz += a.res_part[3 * b];
+    rr += a.res_part[3 * b + 1];
+    bb += a.res_part[3 * b + 2];
+  }
+  const double stop2 = fmax(a.tol_rel * a.tol_rel * rr, a.tol_abs * a.tol_abs * bb);
+  lds_zero(lds, sl.G * 3 * sl.SP);
+  __syncthreads();
+  int t = 0, brk = 0;
+  double rz_prev = 1.0;
+  for (;;) {
+    if (!isfinite(rr) || !isfinite(rz)) {
+      brk = 1;
+      break;
+    }
+    if (!(rr > stop2) || t >= a.max_inner) break;
+    const T tb = T(t == 0 ? 0.0 : rz / rz_prev);
+    T* __restrict__ pold = (t & 1) ? p1 : p0;
+    T* __restrict__ pnew = (t & 1) ? p0 : p1;
+    const bool first = t == 0;
+    double a0 = 0.0;
+    auto load = [=](int64_t idx, bool own, T dinv) {
+      T pn = dinv * r[idx];
+      if (!first) pn += tb * pold[idx];
+      if (own) pnew[idx] = pn;
+      return pn;
+    };
+    auto store = [&](int64_t idx, int, int, int, T qv, T pk, T) {
+      q[idx] = qv;
+      a0 += double(pk) * double(qv);
+    };
+    zmarch(sl, lds, load, store);
+    double acc[1] = {a0};
+    block_sum(acc);
+    const double pq = acc[0];
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      brk = 1;
+      break;
+    }
+    const T alpha = T(rz / pq);
+    double acc2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (!sl.act[m]) continue;
+      for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
+        const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
+        const T pv = pnew[idx];
+        x[idx] = t == 0 ? alpha * pv : x[idx] + alpha * pv;
+        const T rv = r[idx] - alpha * q[idx];
+        r[idx] = rv;
+        const double rd = double(rv);
+        acc2[0] += rd * rd * double(slot_dinv(sl, m, k));
+        acc2[1] += rd * rd;
+      }
+    }
+    block_sum(acc2);
+    rz_prev = rz;
+    rz = acc2[0];
+    rr = acc2[1];
+    ++t;
+  }
+  if (t > 0) {
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (!sl.act[m]) continue;
+      for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
+        const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
+        a.u[idx] += double(x[idx]);
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    a.scal[s].iters = t;
+    a.scal[s].breakdown = brk;
+    a.scal[s].done = 1;
+    atomicAdd(&a.iters_total[0], (unsigned long long)t);
+    atomicAdd(&a.iters_total[1], cg_bytes(sd, t, sizeof(T)));
+  }
+}
+
+// ---------------------------------------------------------------------------- exchange
+
+// (M_F w)(a, b) for the face F of subdomain F.s: tangential 1D mass rows.
+__device__ __forceinline__ double face_mass_apply(const Dev& d, const FaceDesc& F, const double* u, int a, int b) {
+  const SubDesc& sd = d.subs[F.s];
+  const int ax = F.axis;
+  // tangential axes: x-face (y, z), y-face (x, z), z-face (x, y)
+  const int na = ax == 0 ? sd.n[1] : sd.n[0];
+  const int nb = ax == 2 ? sd.n[1] : sd.n[2];
+  const int kla = ax == 0 ? sd.klo[1] : sd.klo[0];
+  const int klb = ax == 2 ? sd.klo[1] : sd.klo[2];
+  const int nea = ax == 0 ? sd.ne2[1] : sd.ne2[0];
+  const int neb = ax == 2 ? sd.ne2[1] : sd.ne2[2];
+  const double msa = ax == 0 ? d.geo.ms[1] : d.geo.ms[0];
+  const double msb = ax == 2 ? d.geo.ms[1] : d.geo.ms[2];
+  const int ta = ax == 0 ? 1 : 0;
+  const int tb = ax == 2 ? 1 : 2;
+  const int nax = ax == 0 ? sd.n[0] : (ax == 1 ? sd.n[1] : sd.n[2]);
+  const int plane = F.side ? nax - 1 : 0;
+  const Row<double> ra = row_of<double>(a + kla, nea, 0.0, msa, 0.0, 0.0);
+  const Row<double> rb = row_of<double>(b + klb, neb, 0.0, msb, 0.0, 0.0);
+  const int sx = 1, sy = sd.n[0], sz = sd.n[0] * sd.n[1];
+  const int64_t sa = ta == 0 ? sx : sy;
+  const int64_t sb = tb == 1 ? sy : sz;
+  const int64_t sn = ax == 0 ? sx : (ax == 1 ? sy : sz);
+  const int64_t base = sd.off + (int64_t)plane * sn;
+  double acc = 0.0;
+#pragma unroll
+  for (int ob = 0; ob < 5; ++ob) {
+    const int bb = b + ob - 2;
+    const double cbv = (ob == 2) ? rb.m0 : ((ob == 1 || ob == 3) ? 2.0 * msb : rb.m2);
+    if (bb < 0 || bb >= nb) continue;
+    double row = 0.0;
+#pragma unroll
+    for (int oa = 0; oa < 5; ++oa) {
+      const int aa = a + oa - 2;
+      const double cav = (oa == 2) ? ra.m0 : ((oa == 1 || oa == 3) ? 2.0 * msa : ra.m2);
+      if (aa < 0 || aa >= na) continue;
+      row += cav * u[base + (int64_t)aa * sa + (int64_t)bb * sb];
+    }
+    acc += cbv * row;
+  }
+  return acc;
+}
+
+// lambda_{s<-j} <- -lambda_{j<-s} + (p_sj + p_js) M_F u_j,
+// lambda_{j<-s} <- -lambda_{s<-j} + (p_sj + p_js) M_F u_s.
+__global__ void k_exchange(Dev d, const int32_t* __restrict__ pair_faces, const double* __restrict__ u,
+                           double* __restrict__ lam) {
+  const FaceDesc F = d.faces[pair_faces[blockIdx.y]];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F.na * F.nb) return;
+  const FaceDesc Gf = d.faces[F.opp];
+  const int a = t % F.na, b = t / F.na;
+  const double mus = face_mass_apply(d, F, u, a, b);
+  const double muj = face_mass_apply(d, Gf, u, a, b);
+  const double c = F.p + Gf.p;
+  const double lf = lam[F.lam_off + t];
+  const double lg = lam[Gf.lam_off + t];
+  lam[F.lam_off + t] = -lg + c * muj;
+  lam[Gf.lam_off + t] = -lf + c * mus;
+}
+
+// ---------------------------------------------------------------------------- glue and residual
+
+// Visit the subdomain copies of local node (i, j, k) of sd in ascending
+// subdomain order: fn(global index of the copy in the local layout).
+template <class Fn>
+__device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i, int j, int k, Fn&& fn) {
+  const int li[3] = {i, j, k};
+  int p0[3], i0[3], i1[3], nc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    nc[a] = 1;
+    p0[a] = sd.pidx[a];
+    i0[a] = li[a];
+    i1[a] = 0;
+    if (li[a] == 0 && sd.face[2 * a] >= 0) {
+      const int jn = d.faces[sd.face[2 * a]].j;
+      nc[a] = 2;
+      p0[a] = sd.pidx[a] - 1;
+      i0[a] = d.subs[jn].n[a] - 1;
+      i1[a] = li[a];
+    } else if (li[a] == sd.n[a] - 1 && sd.face[2 * a + 1] >= 0) {
+      nc[a] = 2;
+      i1[a] = 0;
+    }
+  }
+  const int Px = d.geo.nparts[0], Py = d.geo.nparts[1];
+  for (int cz = 0; cz < nc[2]; ++cz)
+    for (int cy = 0; cy < nc[1]; ++cy)
+      for (int cx = 0; cx < nc[0]; ++cx) {
+        const int s2 = (p0[0] + cx) + Px * ((p0[1] + cy) + Py * (p0[2] + cz));
+        const SubDesc& o = d.subs[s2];
+        const int ix = cx ? i1[0] : i0[0], iy = cy ? i1[1] : i0[1], iz = cz ? i1[2] : i0[2];
+        fn(o.off + ix + (int64_t)o.n[0] * (iy + (int64_t)o.n[1] * iz));
+      }
+  return nc[0] * nc[1] * nc[2];
+}
+
+__global__ void k_glue(Dev d, const double* __restrict__ u, double* __restrict__ ut) {
+  const SubDesc sd = d.subs[blockIdx.y];
+  const int n = sd.n[0] * sd.n[1] * sd.n[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = t % sd.n[0], j = (t / sd.n[0]) % sd.n[1], k = t / (sd.n[0] * sd.n[1]);
+  double s = 0.0;
+  const int n_c = for_copies(d, sd, i, j, k, [&](int64_t idx) { s += u[idx]; });
+  ut[sd.off + t] = s / double(n_c);
+}
+
+// A node is owned by the copy that is not at the lower end of any interface.
+__global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const double* __restrict__ f,
+                                const double* __restrict__ ut, double* __restrict__ phi,
+                                double* __restrict__ part) {
+  const SubDesc sd = d.subs[blockIdx.y];
+  const int n = sd.n[0] * sd.n[1] * sd.n[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (t < n) {
+    const int i = t % sd.n[0], j = (t / sd.n[0]) % sd.n[1], k = t / (sd.n[0] * sd.n[1]);
+    const bool owned = !((i == 0 && sd.face[0] >= 0) || (j == 0 && sd.face[2] >= 0) || (k == 0 && sd.face[4] >= 0));
+    if (owned) {
+      double rs = 0.0, fs = 0.0;
+      for_copies(d, sd, i, j, k, [&](int64_t idx) {
+        rs += rho[idx];
+        fs += f[idx];
+      });
+      acc[0] = rs * rs;
+      acc[1] = fs * fs;
+      if (phi) {
+        const int64_t g = (sd.lo[0] + i) + (int64_t)d.geo.nn[0] * ((sd.lo[1] + j) + (int64_t)d.geo.nn[1] * (sd.lo[2] + k));
+        phi[g] = ut[sd.off + t];
+      }
+    }
+  }
+  block_sum(acc);
+  if (threadIdx.x == 0) {
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * b] = acc[0];
+    part[2 * b + 1] = acc[1];
+  }
+}
+
+__global__ void k_final_norm(const double* __restrict__ part, int nblk, double* dev_out, double* host_out) {
+  double acc[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    acc[0] += part[2 * b];
+    acc[1] += part[2 * b + 1];
+  }
+  block_sum(acc);
+  if (threadIdx.x == 0) {
+    const double res = acc[1] > 0.0 ? sqrt(acc[0] / acc[1]) : (acc[0] > 0.0 ? INFINITY : 0.0);
+    dev_out[0] = res;
+    dev_out[1] = acc[0];
+    dev_out[2] = acc[1];
+    if (host_out) host_out[0] = res;
+  }
+}
+
+__global__ void k_fill(double* x, int64_t n, double v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------- loads
+
+// f_s = 4 pi G sum over the elements of s containing the node of drho_e * prod_d w_d,
+// w = h/6 at an element end, 2h/3 at its mid-point.
+__global__ void k_load_density(Dev d, const double* __restrict__ drho, double G, double* __restrict__ f) {
+  const SubDesc sd = d.subs[blockIdx.y];
+  const int n = sd.n[0] * sd.n[1] * sd.n[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int li[3] = {t % sd.n[0], (t / sd.n[0]) % sd.n[1], t / (sd.n[0] * sd.n[1])};
+  int el[3][2], ne[3];
+  double w[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int gc = sd.lo[a] + li[a];
+    const int e0 = sd.e0[a], e1 = sd.e0[a] + sd.ne2[a] / 2;
+    const double h = d.geo.h[a];
+    ne[a] = 0;
+    if (gc & 1) {
+      el[a][0] = (gc - 1) / 2;
+      w[a][0] = 2.0 * h / 3.0;
+      ne[a] = 1;
+    } else {
+      const int lo = gc / 2 - 1, hi = gc / 2;
+      if (lo >= e0 && lo < e1) {
+        el[a][ne[a]] = lo;
+        w[a][ne[a]] = h / 6.0;
+        ++ne[a];
+      }
+      if (hi >= e0 && hi < e1) {
+        el[a][ne[a]] = hi;
+        w[a][ne[a]] = h / 6.0;
+        ++ne[a];
+      }
+    }
+  }
+  const int Ex = d.geo.ne[0], Ey = d.geo.ne[1];
+  double acc = 0.0;
+  for (int cz = 0; cz < ne[2]; ++cz)
+    for (int cy = 0; cy < ne[1]; ++cy)
+      for (int cx = 0; cx < ne[0]; ++cx)
+        acc += drho[el[0][cx] + (int64_t)Ex * (el[1][cy] + (int64_t)Ey * el[2][cz])] * (w[0][cx] * w[1][cy] * w[2][cz]);
+  f[sd.off + t] = 4.0 * M_PI * G * acc;
+}
+
+__global__ void k_load_nodes(Dev d, const double* __restrict__ fn, double* __restrict__ f) {
+  const SubDesc sd = d.subs[blockIdx.y];
+  const int n = sd.n[0] * sd.n[1] * sd.n[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int li[3] = {t % sd.n[0], (t / sd.n[0]) % sd.n[1], t / (sd.n[0] * sd.n[1])};
+  int mult = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if ((li[a] == 0 && sd.face[2 * a] >= 0) || (li[a] == sd.n[a] - 1 && sd.face[2 * a + 1] >= 0)) mult *= 2;
+  const int64_t g = (sd.lo[0] + li[0]) + (int64_t)d.geo.nn[0] * ((sd.lo[1] + li[1]) + (int64_t)d.geo.nn[1] * (sd.lo[2] + li[2]));
+  f[sd.off + t] = fn[g] / double(mult);
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+#define SOS_DISPATCH_CPT(cpt, KERNEL_CALL) \
+  switch (cpt) {                           \
+    case 1: {                              \
+      constexpr int C = 1;                 \
+      KERNEL_CALL;                         \
+    } break;                               \
+    case 2: {                              \
+      constexpr int C = 2;                 \
+      KERNEL_CALL;                         \
+    } break;                               \
+    case 4: {                              \
+      constexpr int C = 4;                 \
+      KERNEL_CALL;                         \
+    } break;                               \
+    default:                               \
+      return hipErrorInvalidValue;         \
+  }
+
+static dim3 node_grid(const Dev& d, int max_n, int threads) { return dim3((max_n + threads - 1) / threads, d.geo.n_sub); }
+
+hipError_t launch_load_density(const Dev& d, int max_n, const double* drho, double G, double* f_loc,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_load_density, node_grid(d, max_n, 256), dim3(256), 0, st, d, drho, G, f_loc);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, double* f_loc, hipStream_t st) {
+  hipLaunchKernelGGL(k_load_nodes, node_grid(d, max_n, 256), dim3(256), 0, st, d, f_nodes, f_loc);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u, const double* f,
+                           const double* lam, void* r_out, double* part, hipStream_t st) {
+  if (fp32) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+                                               st, d, L.blocks, u, f, lam, (float*)r_out, part));
+  } else {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+                                               st, d, L.blocks, u, f, lam, (double*)r_out, part));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel, double tol_abs,
+                          CgScal* scal, int32_t* ndone, hipStream_t st) {
+  const int n = d.geo.n_sub;
+  hipLaunchKernelGGL(k_cg_init, dim3((n + 255) / 256), dim3(256), 0, st, n, L.bfirst, part, tol_rel, tol_abs,
+                     scal, ndone);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_apply(const Dev& d, const SegLaunch& L, int fp32, int t, int max_inner, const void* r,
+                           const void* p_old, void* p_new, void* q, double* part, CgScal* scal, int32_t* ndone,
+                           unsigned long long* counters, hipStream_t st) {
+  if (fp32) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds32,
+                                               st, d, L.blocks, L.bfirst, t, max_inner, (const float*)r,
+                                               (const float*)p_old, (float*)p_new, (float*)q, part, scal, ndone,
+                                               counters));
+  } else {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+                                               st, d, L.blocks, L.bfirst, t, max_inner, (const double*)r,
+                                               (const double*)p_old, (double*)p_new, (double*)q, part, scal,
+                                               ndone, counters));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const Dev& d, const SegLaunch& L, int fp32, int t, void* x, const void* p, void* r,
+                            const void* q, double* part, CgScal* scal, int32_t* ndone, hipStream_t st) {
+  if (fp32) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<float, C>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
+                                               L.blocks, L.bfirst, t, (float*)x, (const float*)p, (float*)r,
+                                               (const float*)q, part, scal, ndone));
+  } else {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<double, C>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
+                                               L.blocks, L.bfirst, t, (double*)x, (const double*)p, (double*)r,
+                                               (const double*)q, part, scal, ndone));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, double* u, const void* x,
+                                 const CgScal* scal, hipStream_t st) {
+  if (fp32) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_add_correction<float, C>), dim3(L.nblocks), dim3(L.threads), 0,
+                                               st, d, L.blocks, u, (const float*)x, scal));
+  } else {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_add_correction<double, C>), dim3(L.nblocks), dim3(L.threads), 0,
+                                               st, d, L.blocks, u, (const double*)x, scal));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
+                           const FusedArgs& a, hipStream_t st) {
+  if (fp32) {
+    SOS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k_fused_cg<float, C>), dim3(d.geo.n_sub), dim3(threads), lds, st, d,
+                                             L.bfirst, a));
+  } else {
+    SOS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k_fused_cg<double, C>), dim3(d.geo.n_sub), dim3(threads), lds, st, d,
+                                             L.bfirst, a));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_face,
+                           const double* u, double* lam, hipStream_t st) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exchange, dim3((max_face + 255) / 256, n_pairs), dim3(256), 0, st, d, pair_faces, u, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_glue(const Dev& d, int max_n, const double* u, double* ut, hipStream_t st) {
+  hipLaunchKernelGGL(k_glue, node_grid(d, max_n, 256), dim3(256), 0, st, d, u, ut);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_residual(const Dev& d, const SegLaunch& L, const double* ut, const double* f, double* rho,
+                                 hipStream_t st) {
+  SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_local_residual<C>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
+                                             d, L.blocks, ut, f, rho));
+  return hipGetLastError();
+}
+
+int assemble_blocks(const Dev& d, int max_n) { return ((max_n + kAssembleThreads - 1) / kAssembleThreads) * d.geo.n_sub; }
+
+hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, const double* f, const double* ut,
+                                double* phi, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_assemble_norm, node_grid(d, max_n, kAssembleThreads), dim3(kAssembleThreads), 0, st, d, rho,
+                     f, ut, phi, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_norm(const double* part, int32_t nblk, double* dev_out, double* host_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, nblk, dev_out, host_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const Dev& d, const SegLaunch& L, int fp32, const void* x, void* y, hipStream_t st) {
+  if (fp32) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_apply<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds32, st, d,
+                                               L.blocks, (const float*)x, (float*)y));
+  } else {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_apply<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
+                                               d, L.blocks, (const double*)x, (double*)y));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sos

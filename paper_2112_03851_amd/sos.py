@@ -1,0 +1,305 @@
+"""ctypes binding of libsos.so (argument marshalling only).
+
+Every call goes to the HIP library built from csrc/; there is no Python or CPU
+implementation of any step. If the library is missing this module raises.
+Device arrays are torch tensors on the current HIP device (FP64 unless
+stated); PyTorch supplies memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libsos.so")
+HEADER = os.path.join(ROOT, "include", "sos.h")
+
+SOS_OK, SOS_EINVAL, SOS_ENOMEM, SOS_EHIP, SOS_ENOCONV, SOS_EBREAKDOWN, SOS_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SOS_DIRICHLET, SOS_NEUMANN = 0, 1
+SOS_FP64, SOS_FP32_INNER = 0, 1
+SOS_STEPWISE, SOS_BATCHED = 0, 1
+ERROR_NAMES = {0: "SOS_OK", -1: "SOS_EINVAL", -2: "SOS_ENOMEM", -3: "SOS_EHIP", -4: "SOS_ENOCONV",
+               -5: "SOS_EBREAKDOWN", -6: "SOS_ESTATE"}
+
+
+class SosError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Mesh(C.Structure):
+    _fields_ = [("ne", C.c_int32 * 3), ("len", C.c_double * 3), ("bc", C.c_int32 * 6)]
+
+
+class Partition(C.Structure):
+    _fields_ = [("nparts", C.c_int32 * 3), ("cuts", C.POINTER(C.c_int32) * 3)]
+
+
+class Robin(C.Structure):
+    _fields_ = [("order", C.c_int32), ("p0", C.c_double), ("p", C.POINTER(C.c_double))]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("max_outer", C.c_int32),
+                ("max_inner", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
+                ("inner_tol", C.c_double), ("inner_abs", C.c_double), ("G", C.c_double),
+                ("stream", C.c_void_p), ("block", C.c_int32), ("timing", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("checks", C.c_int32), ("inner_iters", C.c_int64),
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("kernel_ms", C.c_double),
+                ("kernel_launches", C.c_int64), ("kernel_bytes", C.c_double), ("block", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def declared_functions():
+    """Names of the functions declared in include/sos.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sos_[a-z_]+)\s*\(", text)))
+
+
+def lib():
+    """Load libsos.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2112_03851_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, I, D = C.c_void_p, C.c_int32, C.c_double
+    sig = {
+        "sos_opts_default": (C.c_int, [C.POINTER(Opts), I]),
+        "sos_setup": (C.c_int, [C.POINTER(Mesh), C.POINTER(Partition), C.POINTER(Robin), C.POINTER(Opts),
+                                C.POINTER(P)]),
+        "sos_set_robin": (C.c_int, [P, C.POINTER(Robin)]),
+        "sos_set_opts": (C.c_int, [P, C.POINTER(Opts)]),
+        "sos_faces": (C.c_int, [P, C.POINTER(I), C.POINTER(I)]),
+        "sos_layout": (C.c_int, [P, C.POINTER(I), C.POINTER(C.c_int64), C.POINTER(I), C.POINTER(I),
+                                 C.POINTER(C.c_int64)]),
+        "sos_solve": (C.c_int, [P, P, D, P, C.POINTER(Stats)]),
+        "sos_solve_load": (C.c_int, [P, P, D, P, C.POINTER(Stats)]),
+        "sos_apply_local": (C.c_int, [P, I, P, P]),
+        "sos_get_state": (C.c_int, [P, P, P]),
+        "sos_set_state": (C.c_int, [P, P, P]),
+        "sos_set_density": (C.c_int, [P, P]),
+        "sos_iterate": (C.c_int, [P, I, C.POINTER(Stats)]),
+        "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
+        "sos_destroy": (None, [P]),
+        "sos_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(code):
+    if code != SOS_OK:
+        raise SosError(code, lib().sos_last_error().decode())
+
+
+def default_opts(precision=SOS_FP64):
+    o = Opts()
+    _check(lib().sos_opts_default(C.byref(o), int(precision)))
+    return o
+
+
+def _ptr(t, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _sync_torch():
+    import torch
+    torch.cuda.current_stream().synchronize()
+
+
+class Problem:
+    """A box mesh, a box partition and Robin coefficients set up on the GPU.
+
+    ne, lengths, bc: mesh (bc per face x-,x+,y-,y+,z-,z+; 0 Dirichlet, 1 Neumann)
+    cuts: per axis a sequence of interior cut element indices (equal split if
+          nparts is given instead)
+    p: Robin coefficient (float, or one value per directed face)
+    precision: 'fp64' or 'fp32' (FP32 inner CG, FP64 outer)
+    mode: 'stepwise' or 'batched'
+    """
+
+    def __init__(self, ne, lengths=(1.0, 1.0, 1.0), bc=(0,) * 6, cuts=None, nparts=None, p=1.0,
+                 precision="fp64", mode=None, **opts):
+        L = lib()
+        prec = SOS_FP32_INNER if precision in ("fp32", SOS_FP32_INNER) else SOS_FP64
+        o = default_opts(prec)
+        if mode is not None:
+            o.mode = SOS_BATCHED if mode in ("batched", SOS_BATCHED) else SOS_STEPWISE
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self.mesh = Mesh((C.c_int32 * 3)(*ne), (C.c_double * 3)(*lengths), (C.c_int32 * 6)(*bc))
+        self._cut_arrays = []
+        part = Partition()
+        if cuts is not None:
+            for a in range(3):
+                c = [int(v) for v in cuts[a]]
+                part.nparts[a] = len(c) + 1
+                arr = (C.c_int32 * max(1, len(c)))(*c) if c else None
+                self._cut_arrays.append(arr)
+                part.cuts[a] = C.cast(arr, C.POINTER(C.c_int32)) if arr is not None else C.POINTER(C.c_int32)()
+        else:
+            nparts = nparts or (1, 1, 1)
+            for a in range(3):
+                part.nparts[a] = int(nparts[a])
+                part.cuts[a] = C.POINTER(C.c_int32)()
+        self.part = part
+        self._robin = self._make_robin(p)
+        self.opts = o
+        self.ne = tuple(int(v) for v in ne)
+        self.n_nodes = int(np.prod([2 * v + 1 for v in ne]))
+        self.n_elem = int(np.prod(ne))
+        h = C.c_void_p()
+        _check(L.sos_setup(C.byref(self.mesh), C.byref(part), C.byref(self._robin[0]), C.byref(o),
+                           C.byref(h)))
+        self.h = h
+        self.precision = prec
+
+    @staticmethod
+    def _make_robin(p):
+        r = Robin()
+        r.order = 0
+        if np.ndim(p) == 0:
+            r.p0 = float(p)
+            r.p = C.POINTER(C.c_double)()
+            return (r, None)
+        arr = (C.c_double * len(p))(*[float(v) for v in p])
+        r.p0 = 0.0
+        r.p = C.cast(arr, C.POINTER(C.c_double))
+        return (r, arr)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sos_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ host queries
+    def faces(self):
+        n = C.c_int32()
+        _check(lib().sos_faces(self.h, C.byref(n), None))
+        buf = (C.c_int32 * (4 * n.value))()
+        _check(lib().sos_faces(self.h, C.byref(n), buf))
+        return np.array(buf, dtype=np.int32).reshape(-1, 4)
+
+    def layout(self):
+        ns = C.c_int32()
+        _check(lib().sos_layout(self.h, C.byref(ns), None, None, None, None))
+        n = ns.value
+        nf = len(self.faces())
+        off = (C.c_int64 * (n + 1))()
+        dims = (C.c_int32 * (3 * n))()
+        lo = (C.c_int32 * (3 * n))()
+        foff = (C.c_int64 * (nf + 1))()
+        _check(lib().sos_layout(self.h, C.byref(ns), off, dims, lo, foff))
+        return {"offsets": np.array(off, np.int64), "dims": np.array(dims, np.int32).reshape(-1, 3),
+                "lo": np.array(lo, np.int32).reshape(-1, 3), "face_off": np.array(foff, np.int64)}
+
+    def set_robin(self, p):
+        self._robin = self._make_robin(p)
+        _check(lib().sos_set_robin(self.h, C.byref(self._robin[0])))
+
+    def set_opts(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        _check(lib().sos_set_opts(self.h, C.byref(self.opts)))
+
+    # ------------------------------------------------------------------ device calls
+    def solve(self, drho, tol, phi=None):
+        import torch
+        phi = torch.empty(self.n_nodes, dtype=torch.float64, device=drho.device) if phi is None else phi
+        st = Stats()
+        _sync_torch()
+        code = lib().sos_solve(self.h, _ptr(drho, torch.float64), float(tol), _ptr(phi, torch.float64),
+                               C.byref(st))
+        if code not in (SOS_OK, SOS_ENOCONV):
+            _check(code)
+        return phi, dict(st.as_dict(), converged=code == SOS_OK)
+
+    def solve_load(self, f_nodes, tol, phi=None):
+        import torch
+        phi = torch.empty(self.n_nodes, dtype=torch.float64, device=f_nodes.device) if phi is None else phi
+        st = Stats()
+        _sync_torch()
+        code = lib().sos_solve_load(self.h, _ptr(f_nodes, torch.float64), float(tol),
+                                    _ptr(phi, torch.float64), C.byref(st))
+        if code not in (SOS_OK, SOS_ENOCONV):
+            _check(code)
+        return phi, dict(st.as_dict(), converged=code == SOS_OK)
+
+    def apply_local(self, x):
+        import torch
+        prec = SOS_FP32_INNER if x.dtype == torch.float32 else SOS_FP64
+        y = torch.empty_like(x)
+        _sync_torch()
+        _check(lib().sos_apply_local(self.h, prec, _ptr(x), _ptr(y)))
+        return y
+
+    def n_local(self):
+        return int(self.layout()["offsets"][-1])
+
+    def get_state(self):
+        import torch
+        lay = self.layout()
+        u = torch.empty(int(lay["offsets"][-1]), dtype=torch.float64, device="cuda")
+        lam = torch.empty(max(1, int(lay["face_off"][-1])), dtype=torch.float64, device="cuda")
+        _sync_torch()
+        _check(lib().sos_get_state(self.h, _ptr(u), _ptr(lam)))
+        return u, lam[: int(lay["face_off"][-1])]
+
+    def set_state(self, u=None, lam=None):
+        import torch
+        _sync_torch()
+        _check(lib().sos_set_state(self.h, _ptr(u, torch.float64) if u is not None else None,
+                                   _ptr(lam, torch.float64) if lam is not None else None))
+
+    def set_density(self, drho):
+        import torch
+        _sync_torch()
+        _check(lib().sos_set_density(self.h, _ptr(drho, torch.float64)))
+
+    def iterate(self, n):
+        st = Stats()
+        _check(lib().sos_iterate(self.h, int(n), C.byref(st)))
+        return st.as_dict()
+
+    def residual(self, want_phi=True):
+        import torch
+        phi = torch.empty(self.n_nodes, dtype=torch.float64, device="cuda") if want_phi else None
+        res = C.c_double()
+        _sync_torch()
+        _check(lib().sos_residual(self.h, _ptr(phi) if phi is not None else None, C.byref(res)))
+        return phi, res.value

@@ -1,0 +1,71 @@
+"""Test helpers: build the oracle's view and the library's view of one workload
+and move per-subdomain vectors between the two layouts (test infrastructure)."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import assemble as A
+from oracle import mesh as M
+from oracle import partition as P
+from oracle import subdomain as SD
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+class Case:
+    def __init__(self, ne, lengths=(1.0, 1.0, 1.0), bc=(0,) * 6, cuts=((), (), ()), p=8.0, G=6.672e-11):
+        self.ne, self.lengths, self.bc, self.cuts, self.p, self.G = tuple(ne), tuple(lengths), tuple(bc), cuts, p, G
+        self.mesh = M.BoxMesh(ne, lengths, bc)
+        self.part = P.BoxPartition(self.mesh, cuts)
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.ne, wl.lengths, wl.bc, wl.cuts, wl.p, wl.G)
+
+    def problem(self, **kw):
+        from paper_2112_03851_amd.sos import Problem
+        return Problem(self.ne, self.lengths, self.bc, cuts=self.cuts, p=self.p, **kw)
+
+    def check_layout(self, prob):
+        lay = prob.layout()
+        assert len(lay["dims"]) == self.part.n_sub
+        for s, sub in enumerate(self.part.subs):
+            assert tuple(lay["dims"][s]) == sub.shape, (s, lay["dims"][s], sub.shape)
+            assert tuple(lay["lo"][s]) == sub.lo
+        f = prob.faces()
+        assert len(f) == len(self.part.faces)
+        for a, b in zip(f, self.part.faces):
+            assert tuple(a) == (b.s, b.j, b.axis, b.side)
+        return lay
+
+    def to_local(self, lay, parts, dtype=np.float64):
+        out = np.zeros(int(lay["offsets"][-1]), dtype)
+        for s, v in enumerate(parts):
+            o = int(lay["offsets"][s])
+            out[o:o + v.size] = v
+        return out
+
+    def from_local(self, lay, vec):
+        return [np.asarray(vec[int(lay["offsets"][s]):int(lay["offsets"][s]) + sub.n])
+                for s, sub in enumerate(self.part.subs)]
+
+    def lam_to_faces(self, lay, lam):
+        fo = lay["face_off"]
+        return [np.asarray(lam[int(fo[f]):int(fo[f + 1])]) for f in range(len(self.part.faces))]
+
+    def faces_to_lam(self, lay, lam_faces):
+        out = np.zeros(int(lay["face_off"][-1]))
+        for f, v in enumerate(lam_faces):
+            out[int(lay["face_off"][f]):int(lay["face_off"][f + 1])] = v
+        return out
+
+    def density_loads(self, drho):
+        f = A.load_from_density(self.mesh, drho, self.G)
+        fs = [SD.density_load(self.part, s, drho, self.G) for s in self.part.subs]
+        return f, fs

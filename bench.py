@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: Robin-Schwarz solves per second to a 1e-8 relative residual on
+one MI355X, batched FP32-inner form vs the plain FP64 stepwise form.
+
+A step is one complete Schwarz solve of the workload (load from the density,
+outer iterations of residual + fused subdomain CG + Robin exchange, global
+residual checks) with its inputs already in HBM. Default workload: 64^3 Q2
+elements on the unit cube, 4x4x4 subdomains, Robin p = 8/h, layered
+crater-like density anomaly with 10 Gaussian blobs (seeded, synthetic).
+
+Prints one JSON line (rank 0). The roofline entry times the fused CG kernel
+with HIP events on the library's stream over the timed region; algorithmic
+bytes are counted by the kernel itself (10 vectors read or written per CG
+iteration and unknown). The CPU baseline times the oracle (exact subdomain
+solves) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "fused_cg_c2_pmc.json")
+GOLDEN_COUNTS = os.path.join(ROOT, "tests", "golden", "oracle_outer_counts.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2112_03851_amd", "csrc", "sos_kernels.hip")
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def baseline_metric():
+    try:
+        return json.load(open(os.path.join(ROOT, "BASELINE.json")))["metric"]
+    except Exception:
+        return "Schwarz solves/s to 1e-8 rel residual"
+
+
+def measured_traffic(launch_bytes):
+    """HBM bytes per fused-kernel launch from committed rocprofv3 counters,
+    if they were taken on the current kernel source."""
+    try:
+        pmc = json.load(open(PMC_FILE))
+    except Exception:
+        return None
+    if pmc.get("kernel_sha") != kernel_sha():
+        return None
+    return pmc.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s, phi_gpu):
+    """The oracle (exact FDM subdomain solves, Jacobi exchange, global residual
+    after every outer iteration) on a bounded number of outer iterations of the
+    same workload, scaled to solves/s with the oracle's own outer iteration
+    count for a full solve."""
+    import numpy as np
+    from oracle import assemble as A
+    from oracle import direct as D
+    from oracle import mesh as M
+    from oracle import partition as P
+    from oracle import schwarz as S
+    from oracle import subdomain as SD
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        blas_threads = 1
+    m = M.BoxMesh(wl.ne, wl.lengths, wl.bc)
+    part = P.BoxPartition(m, wl.cuts)
+    drho = wl.drho()
+    f = A.load_from_density(m, drho, wl.G)
+    fs = [SD.density_load(part, s, drho, wl.G) for s in part.subs]
+    t0 = time.perf_counter()
+    orc = S.SchwarzOracle(part, wl.p, "fdm")
+    setup_s = time.perf_counter() - t0
+    lam = orc.zero_data()
+    n = 0
+    t0 = time.perf_counter()
+    while n < 3 or time.perf_counter() - t0 < budget_s:
+        u = orc.subdomain_solves(fs, lam)
+        lam = orc.exchange(u, lam)
+        A.residual_norm(m, orc.glue(u), f)
+        n += 1
+    el = time.perf_counter() - t0
+    n_outer = None
+    try:
+        n_outer = json.load(open(GOLDEN_COUNTS))[f"{wl.name}_seed{wl.seed}"]["outer_iters"]
+    except Exception:
+        pass
+    out = {"value": (n / el) / n_outer if n_outer else None, "unit": "solves/s", "cores": int(blas_threads),
+           "kind": "oracle",
+           "sample": f"{n} outer iterations of the oracle's Schwarz solve of this workload in {el:.1f} s "
+                     f"(setup {setup_s:.1f} s excluded), scaled by its {n_outer} outer iterations per "
+                     f"solve to 1e-8",
+           "outer_iters_per_s": n / el}
+    if phi_gpu is not None:
+        t0 = time.perf_counter()
+        ud = D.solve_direct(m, f, "fdm")
+        out["direct_solve_s"] = time.perf_counter() - t0
+        out["gpu_max_rel_err_vs_oracle_direct"] = float(np.abs(phi_gpu - ud).max() / np.abs(ud).max())
+        out["gpu_rel_residual_by_oracle"] = A.residual_norm(m, phi_gpu, f)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--inner-tol", type=float, default=0.1)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2112_03851_amd.sos import Problem
+    from synth import workload
+
+    wl = workload(args.workload, seed=args.seed)
+    drho = torch.tensor(wl.drho(), device="cuda")
+    prob = Problem(wl.ne, wl.lengths, wl.bc, cuts=wl.cuts, p=wl.p, G=wl.G, precision="fp32", mode="batched",
+                   check_every=args.check_every, inner_tol=args.inner_tol, timing=1, block=args.block)
+    for _ in range(args.warmup):
+        prob.solve(drho, wl.tol)
+    tot = {"kernel_ms": 0.0, "kernel_launches": 0, "kernel_bytes": 0.0, "outer_iters": 0, "inner_iters": 0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phi, st = prob.solve(drho, wl.tol)
+        for k in tot:
+            tot[k] += st[k]
+        if not st["converged"]:
+            raise RuntimeError(f"batched solve did not converge: {st}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phi_np = phi.cpu().numpy()
+    launch_bytes = tot["kernel_bytes"] / tot["kernel_launches"]
+    launch_s = tot["kernel_ms"] * 1e-3 / tot["kernel_launches"]
+    achieved = launch_bytes / launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
+                "kernel": "k_fused_cg<float>", "avg_launch_ms": launch_s * 1e3,
+                "algorithmic_bytes_per_launch": launch_bytes}
+    batched = {"outer_iters": tot["outer_iters"] // args.steps, "inner_iters": tot["inner_iters"] // args.steps,
+               "rel_residual": st["rel_residual"], "block": st["block"], "seconds_per_solve": el / args.steps,
+               "inner_tol": args.inner_tol, "check_every": args.check_every}
+    prob.close()
+
+    plain = None
+    if not args.no_plain:
+        p64 = Problem(wl.ne, wl.lengths, wl.bc, cuts=wl.cuts, p=wl.p, G=wl.G, precision="fp64", mode="stepwise",
+                      check_every=1, inner_tol=0.0, inner_abs=1e-12, max_inner=2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s64 = p64.solve(drho, wl.tol)
+        torch.cuda.synchronize()
+        plain = {"form": "FP64 Jacobi-PCG per subdomain, one launch per CG step over all subdomains, "
+                         "inner stop 1e-12 ||b_s||",
+                 "seconds_per_solve": time.perf_counter() - t0, "outer_iters": s64["outer_iters"],
+                 "inner_iters": s64["inner_iters"], "rel_residual": s64["rel_residual"],
+                 "converged": s64["converged"]}
+        p64.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds, phi_np)
+    ms = el / args.steps * 1e3
+    line = {
+        "metric": baseline_metric(), "value": args.steps / el, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: unit cube, {wl.ne[0]}x{wl.ne[1]}x{wl.ne[2]} Q2 elements, "
+                               f"{wl.nparts[0]}x{wl.nparts[1]}x{wl.nparts[2]} subdomains, Robin p={wl.p:g} "
+                               f"(8/h), crater-like anomaly (seed {wl.seed}), tol {wl.tol:g}",
+                   "form": "batched: fused FP32 CG kernel per outer iteration, FP64 outer residual, "
+                           "exchange and refinement",
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "batched": batched, "plain": plain,
+        "batched_vs_plain_speedup": (plain["seconds_per_solve"] / (el / args.steps)) if plain else None,
+        "cpu_baseline": cpu, "kernel_sha": kernel_sha(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

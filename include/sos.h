@@ -99,7 +99,11 @@ typedef struct {
                           right-hand side (default 1e-10 for FP64, 0 for FP32)*/
   double G;            /* gravitational constant (default 6.672e-11, Sec. 2)  */
   void* stream;        /* hipStream_t; NULL = default stream                  */
-  int32_t block;       /* SOS_BATCHED workgroup size (0 = autotune)            */
+  int32_t block;       /* SOS_BATCHED workgroup size; 0 = autotune: the first
+                          batched solve times the candidate block shapes of
+                          the fused kernel and keeps the fastest, cached in
+                          $SOS_TUNE_CACHE (default ~/.cache/sos_autotune.jsonl)
+                          per subdomain geometry, precision and inner tolerance */
   int32_t timing;      /* 1: time every fused-kernel launch with HIP events
                           (launches eagerly: events inside a graph are not
                           readable)                                           */
@@ -118,6 +122,7 @@ typedef struct {
                              iteration and local unknown: 10 words read/written
                              + the per-solve setup and update)   */
   int32_t block;          /* workgroup size used by the fused CG kernel         */
+  int32_t cols_per_thread;/* x-y columns per thread of the fused CG kernel      */
 } sos_stats;
 
 /* Fill *opts with defaults for the given precision. */

@@ -37,7 +37,13 @@ class BoxMesh:
         return np.asarray(ix) + Nx * (np.asarray(iy) + Ny * np.asarray(iz))
 
     def element_nodes(self):
-        """(n_elem, 27) global node ids; local node a = ax + 3ay + 9az."""
+        """(n_elem, 27) global node ids; local node a = ax + 3ay + 9az
+        (computed once per mesh)."""
+        if getattr(self, "_conn", None) is None:
+            self._conn = self._element_nodes()
+        return self._conn
+
+    def _element_nodes(self):
         nx, ny, nz = self.ne
         ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
         ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()

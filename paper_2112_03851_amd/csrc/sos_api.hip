@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "../../include/sos.h"
 #include "sos_internal.h"
 #include "sos_kernels.h"
@@ -68,6 +70,7 @@ struct sos_ctx {
   // workspaces
   double *u = nullptr, *f = nullptr, *lam = nullptr, *ut = nullptr, *rho = nullptr;
   void *r = nullptr, *x = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+  void *r1 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr;  // fused CG only
   double* part = nullptr;       // 3 per segmented block
   double* part_norm = nullptr;  // 2 per assemble block
   int n_norm_blocks = 0;
@@ -84,6 +87,8 @@ struct sos_ctx {
   // fused kernel launch shape
   int fused_threads = 0, fused_cpt = 1;
   size_t fused_lds = 0;
+  bool tuned = false;    // fused block shape chosen (explicit or autotuned)
+  double tune_ms = 0.0;  // duration of the chosen shape in the tuning run
   size_t lds_limit = 0;
   // graph of (check_every outer iterations + check)
   hipGraphExec_t gexec = nullptr;
@@ -108,7 +113,8 @@ void release(sos_ctx* c) {
   if (c->graph) hipGraphDestroy(c->graph);
   for (auto e : c->gevents) hipEventDestroy(e);
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f,
-                  c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->part, c->part_norm, c->d_res,
+                  c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
+                  c->part, c->part_norm, c->d_res,
                   c->scal, c->ndone, c->counters};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -199,25 +205,112 @@ int build_seg(sos_ctx* c) {
   return SOS_OK;
 }
 
-int fused_shape(sos_ctx* c, int threads) {
+int smax_plane(const sos_ctx* c) {
   int smax = 0;
   for (auto& s : c->subs) smax = std::max(smax, s.n[0] * s.n[1]);
-  if (threads == 0) {
-    int cpt = 1;
-    while (cpt < 4 && (smax + cpt - 1) / cpt > 1024) cpt *= 2;
-    threads = ((smax + cpt - 1) / cpt + 63) / 64 * 64;
-    threads = std::max(threads, 256);
-  }
-  int cpt = 1;
-  while (cpt < 4 && cpt * threads < smax) cpt *= 2;
-  if (cpt * threads < smax) return fail(SOS_EINVAL, "block of %d threads cannot cover a %d-node plane", threads, smax);
+  return smax;
+}
+
+size_t fused_lds_need(const sos_ctx* c, int threads, int cpt) {
   size_t es = c->fp32 ? 4 : 8, lds = 0;
   for (auto& s : c->subs) lds = std::max(lds, march_lds_bytes(s.n[0], s.n[1], s.n[2], threads, cpt, es));
+  return lds;
+}
+
+// Sets the fused kernel's block shape; cpt = 0 picks the fewest columns per
+// thread that cover the largest x-y plane.
+int fused_shape(sos_ctx* c, int threads, int cpt = 0) {
+  const int smax = smax_plane(c);
+  if (threads == 0) {
+    int k = 1;
+    while (k < 4 && (smax + k - 1) / k > 1024) k *= 2;
+    threads = std::max(((smax + k - 1) / k + 63) / 64 * 64, 256);
+  }
+  if (cpt == 0) {
+    cpt = 1;
+    while (cpt < 4 && cpt * threads < smax) ++cpt;
+  }
+  if (cpt * threads < smax) return fail(SOS_EINVAL, "block of %d threads cannot cover a %d-node plane", threads, smax);
+  if (threads > launch_bound(cpt))
+    return fail(SOS_EINVAL, "block of %d threads with %d columns each exceeds the kernel bound %d", threads, cpt,
+                launch_bound(cpt));
+  const size_t lds = fused_lds_need(c, threads, cpt);
   if (lds > c->lds_limit) return fail(SOS_EINVAL, "fused kernel needs %zu bytes of LDS (limit %zu)", lds, c->lds_limit);
   c->fused_threads = threads;
   c->fused_cpt = cpt;
   c->fused_lds = lds;
   return SOS_OK;
+}
+
+// Candidate block shapes of the fused kernel: for 1..4 columns per thread,
+// the smallest block covering the largest plane and 1.5x, 2x, 3x that size
+// (more segments per block on small planes), within the kernel bounds and LDS.
+std::vector<std::pair<int, int>> fused_candidates(const sos_ctx* c) {
+  const int smax = smax_plane(c);
+  std::vector<std::pair<int, int>> out;
+  for (int cpt = 1; cpt <= 4; ++cpt) {
+    const int tmin = std::max(64, ((smax + cpt - 1) / cpt + 63) / 64 * 64);
+    for (int mul2 : {2, 3, 4, 6}) {
+      const int t = (tmin * mul2 / 2 + 63) / 64 * 64;
+      if (t > launch_bound(cpt) || fused_lds_need(c, t, cpt) > c->lds_limit) continue;
+      if (std::find(out.begin(), out.end(), std::make_pair(t, cpt)) == out.end()) out.emplace_back(t, cpt);
+    }
+  }
+  return out;
+}
+
+std::string tune_key(const sos_ctx* c) {
+  // geometry of the subdomain set, precision and inner tolerance
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  for (auto& s : c->subs)
+    for (int a = 0; a < 3; ++a) mix((uint64_t)s.n[a]);
+  mix((uint64_t)c->subs.size());
+  char buf[160];
+  snprintf(buf, sizeof buf, "gfx950|%s|%016llx|tol%.3g|abs%.3g|max%d", c->fp32 ? "fp32" : "fp64",
+           (unsigned long long)h, c->opts.inner_tol, c->opts.inner_abs, c->opts.max_inner);
+  return buf;
+}
+
+std::string tune_cache_path() {
+  const char* p = getenv("SOS_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/sos_autotune.jsonl";
+}
+
+bool tune_lookup(const std::string& key, int* threads, int* cpt) {
+  FILE* f = fopen(tune_cache_path().c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  while (fgets(line, sizeof line, f)) {
+    if (!strstr(line, pat.c_str())) continue;
+    const char* t = strstr(line, "\"threads\": ");
+    const char* k = strstr(line, "\"cpt\": ");
+    if (t && k && sscanf(t + 11, "%d", threads) == 1 && sscanf(k + 7, "%d", cpt) == 1) found = true;
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_store(const std::string& key, int threads, int cpt, double ms) {
+  std::string path = tune_cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    std::string cmd;
+    (void)cmd;
+    mkdir(dir.c_str(), 0755);
+  }
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"ms\": %.4f}\n", key.c_str(), threads, cpt, ms);
+  fclose(f);
 }
 
 template <typename T>
@@ -253,10 +346,14 @@ FusedArgs fused_args(sos_ctx* c) {
   a.tol_abs = c->opts.inner_abs;
   a.max_inner = c->opts.max_inner;
   a.r = c->r;
-  a.x = c->x;
+  a.r1 = c->r1;
+  a.w0 = c->q;
+  a.w1 = c->w1;
+  a.s0 = c->s0;
+  a.s1 = c->s1;
   a.p0 = c->p0;
   a.p1 = c->p1;
-  a.q = c->q;
+  a.x = c->x;
   a.u = c->u;
   a.scal = c->scal;
   a.iters_total = c->counters;
@@ -427,6 +524,7 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
     stats->kernel_launches = c->kernel_launches;
     stats->kernel_bytes = (double)c->h_counters[1];
     stats->block = c->fused_threads;
+    stats->cols_per_thread = c->fused_cpt;
   }
   if (!std::isfinite(res)) return fail(SOS_EBREAKDOWN, "non-finite global residual");
   return SOS_OK;
@@ -446,11 +544,62 @@ int reset_state(sos_ctx* c) {
   return SOS_OK;
 }
 
+// Autotuner: time every candidate block shape of the fused kernel on the
+// first inner solve of the current load (u = 0, lambda = 0), keep the
+// fastest, cache it per (arch, subdomain geometry, precision, inner tolerance).
+int autotune(sos_ctx* c) {
+  if (c->tuned) return SOS_OK;
+  c->tuned = true;
+  const std::string key = tune_key(c);
+  int th = 0, cp = 0;
+  if (tune_lookup(key, &th, &cp) && fused_shape(c, th, cp) == SOS_OK) return SOS_OK;
+  auto cands = fused_candidates(c);
+  if (cands.size() <= 1) return SOS_OK;
+  hipStream_t st = c->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = INFINITY;
+  int bt = c->fused_threads, bc = c->fused_cpt;
+  for (auto& cd : cands) {
+    if (fused_shape(c, cd.first, cd.second) != SOS_OK) continue;
+    double ms_min = INFINITY;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
+      HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part, st));
+      HIPCHK(hipEventRecord(e0, st));
+      HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds,
+                             fused_args(c), st));
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      ms_min = std::min(ms_min, (double)ms);
+    }
+    if (ms_min < best) {
+      best = ms_min;
+      bt = cd.first;
+      bc = cd.second;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int rc = fused_shape(c, bt, bc);
+  if (rc) return rc;
+  c->tune_ms = best;
+  invalidate_graph(c);
+  tune_store(key, bt, bc, best);
+  return SOS_OK;
+}
+
 int solve_common(sos_ctx* c, double tol, double* phi, sos_stats* stats) {
   if (!(tol > 0.0)) return fail(SOS_EINVAL, "tol must be > 0");
   if (!phi) return fail(SOS_EINVAL, "phi_nodes is NULL");
   int rc = reset_state(c);
   if (rc) return rc;
+  if (c->opts.mode == SOS_BATCHED && (rc = autotune(c))) return rc;
   bool conv = false;
   rc = run_outer(c, tol, c->opts.max_outer, stats, &conv);
   if (rc) return rc;
@@ -615,6 +764,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
     return fail(SOS_ESTATE, "no usable HIP device");
   }
   c->lds_limit = prop.sharedMemPerBlock;
+  c->tuned = opts->block != 0;
   if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block))) {
     release(c);
     return rc;
@@ -637,7 +787,9 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
       (rc = dalloc(&c->ut, c->n_local)) || (rc = dalloc(&c->rho, c->n_local)) ||
       (rc = dalloc_v(&c->r, c->n_local * es)) || (rc = dalloc_v(&c->x, c->n_local * es)) ||
       (rc = dalloc_v(&c->p0, c->n_local * es)) || (rc = dalloc_v(&c->p1, c->n_local * es)) ||
-      (rc = dalloc_v(&c->q, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
+      (rc = dalloc_v(&c->q, c->n_local * es)) || (rc = dalloc_v(&c->r1, c->n_local * es)) ||
+      (rc = dalloc_v(&c->w1, c->n_local * es)) || (rc = dalloc_v(&c->s0, c->n_local * es)) ||
+      (rc = dalloc_v(&c->s1, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
       (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4)) ||
       (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2))) {
     release(c);
@@ -710,12 +862,15 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
   if ((o->precision == SOS_FP32_INNER) != (c->fp32 != 0)) return fail(SOS_EINVAL, "precision is fixed at setup");
   if (o->stream && o->stream != c->stream) return fail(SOS_EINVAL, "the stream is fixed at setup");
   const int old_block = c->opts.block;
+  const double old_tol = c->opts.inner_tol, old_abs = c->opts.inner_abs;
   void* st = c->opts.stream;
   c->opts = *o;
   c->opts.stream = st;
-  if (o->block != old_block) {
+  const bool retune = o->block != old_block || o->inner_tol != old_tol || o->inner_abs != old_abs;
+  if (retune) {
     rc = fused_shape(c, o->block);
     if (rc) return rc;
+    c->tuned = o->block != 0;
   }
   invalidate_graph(c);
   return SOS_OK;

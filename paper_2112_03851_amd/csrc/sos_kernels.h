@@ -16,7 +16,7 @@ struct SegLaunch {
   const int32_t* bfirst;    // device, n_sub+1: blocks of s are [bfirst[s], bfirst[s+1])
   int32_t nblocks;
   int32_t threads;          // threads per block (multiple of 64)
-  int32_t cpt;              // x-y columns per thread (1, 2 or 4)
+  int32_t cpt;              // x-y columns per thread (1 to 4)
   size_t lds64;             // dynamic LDS bytes for FP64 marches
   size_t lds32;             // dynamic LDS bytes for FP32 marches
 };
@@ -77,7 +77,7 @@ struct FusedArgs {
   const double* res_part;  // residual partials (segmented launch L)
   double tol_rel, tol_abs;
   int32_t max_inner;
-  void *r, *x, *p0, *p1, *q;
+  void *r, *r1, *w0, *w1, *s0, *s1, *p0, *p1, *x;  // CG vectors (r = the initial residual)
   double* u;
   CgScal* scal;
   unsigned long long* iters_total;  // [0] CG iterations, [1] algorithmic bytes
@@ -107,5 +107,8 @@ hipError_t launch_apply(const Dev& d, const SegLaunch& L, int fp32, const void* 
                         hipStream_t st);
 
 constexpr int kAssembleThreads = 256;
+
+// Largest block the kernels are compiled for with `cpt` x-y columns per thread.
+int launch_bound(int cpt);
 
 }  // namespace sos

@@ -205,21 +205,33 @@ __device__ __forceinline__ void lds_zero(T* lds, int n) {
   for (int e = threadIdx.x; e < n; e += blockDim.x) lds[e] = T(0);
 }
 
-// The z-march. load(idx, own, dinv) returns the operand at global index idx
-// of a plane inside the subdomain (own: the plane belongs to the slot's
-// segment; dinv: inverse diagonal there). store(idx, i, j, k, q, p_k, dinv)
-// receives the finished output at plane k of the slot's own segment, with the
-// operand value p_k at that node.
-template <typename T, int CPT, class LoadF, class StoreF>
-__device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, LoadF& load, StoreF& store) {
+// The z-march, software-pipelined: fetch(idx, own) issues the global loads of
+// the operand at index idx (a plane inside the subdomain) kPrefetch planes
+// ahead of its use; make(raw, idx, own, dinv) turns them into the operand
+// (own: the plane belongs to the slot's segment; dinv: inverse diagonal).
+// store(idx, i, j, k, q, p_k, dinv) receives the finished output at plane k of
+// the slot's own segment, with the operand value p_k at that node.
+constexpr int kPrefetch = 3;
+
+template <typename T, int CPT, class FetchF, class MakeF, class StoreF>
+__device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, FetchF& fetch, MakeF& make,
+                                       StoreF& store) {
+  using Raw = decltype(fetch(int64_t(0), true));
   T acc[CPT][5];
   T pr[CPT][3];
+  Raw raw[CPT][kPrefetch];
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) acc[m][q] = T(0);
 #pragma unroll
     for (int q = 0; q < 3; ++q) pr[m][q] = T(0);
+#pragma unroll
+    for (int q = 0; q < kPrefetch; ++q) {
+      const int kq = sl.z0[m] - 2 + q;
+      if (sl.act[m] && kq >= 0 && kq < sl.nz)
+        raw[m][q] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq, kq >= sl.z0[m] && kq < sl.z1[m]);
+    }
   }
   const int steps = sl.seglen + 4;
   const int PX = sl.PX, SP = sl.SP;
@@ -234,10 +246,15 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, LoadF& l
       if (inr[m]) {
         const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * kp[m];
         const bool own = kp[m] >= sl.z0[m] && kp[m] < sl.z1[m];
-        v = load(idx, own, slot_dinv(sl, m, kp[m]));
+        v = make(raw[m][0], idx, own, slot_dinv(sl, m, kp[m]));
         lds[sl.lp[m]] = v;
       }
       pr[m][2] = v;
+#pragma unroll
+      for (int q = 0; q + 1 < kPrefetch; ++q) raw[m][q] = raw[m][q + 1];
+      const int kq = kp[m] + kPrefetch;
+      if (sl.act[m] && kq >= 0 && kq < sl.nz)
+        raw[m][kPrefetch - 1] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq, kq >= sl.z0[m] && kq < sl.z1[m]);
     }
     __syncthreads();
 #pragma unroll
@@ -293,11 +310,18 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, LoadF& l
   }
 }
 
+template <typename T>
+struct Pair {
+  T a, b;
+};
+
 // Launch bound per x-y columns per thread (the host never launches more).
 template <int CPT>
 struct Bound {
-  static constexpr int value = CPT == 2 ? 576 : 1024;
+  static constexpr int value = CPT == 2 ? 576 : (CPT == 3 ? 384 : 1024);
 };
+
+int launch_bound(int cpt) { return cpt == 2 ? 576 : (cpt == 3 ? 384 : 1024); }
 
 // Robin data added to the local right-hand side at node (i, j, k).
 struct LamOff {
@@ -333,6 +357,15 @@ __device__ __forceinline__ unsigned long long cg_bytes(const SubDesc& sd, int t,
   return n * ((unsigned long long)(10 * t - 2) * es + es + 16ull);
 }
 
+// Algorithmic bytes of a fused inner solve of t >= 1 iterations: the first
+// sweep reads r and writes w, iteration 0 reads r, w and writes r, w, s, p, x,
+// every later iteration reads and writes r, w, s, p, x; then u += x.
+__device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int t, int es) {
+  if (t <= 0) return 0ull;
+  const unsigned long long n = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
+  return n * ((unsigned long long)(10 * t - 1) * es + es + 16ull);
+}
+
 // ---------------------------------------------------------------------------- outer kernels
 
 // r = f + sum_F R^T lambda_F - A u, rounded to TO; partials (r'D^-1 r, r'r, b'b).
@@ -351,7 +384,8 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int nx = sl.nx, ny = sl.ny, nz = sl.nz;
-  auto load = [=](int64_t idx, bool, double) { return u[idx]; };
+  auto fetch = [=](int64_t idx, bool) { return u[idx]; };
+  auto make = [](double v, int64_t, bool, double) { return v; };
   auto store = [&](int64_t idx, int i, int j, int k, double q, double, double dinv) {
     const double b = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
     const TO rt = TO(b - q);
@@ -361,7 +395,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
     a1 += rd * rd;
     a2 += b * b;
   };
-  zmarch(sl, lds, load, store);
+  zmarch(sl, lds, fetch, make, store);
   double acc[3] = {a0, a1, a2};
   block_sum(acc);
   if (threadIdx.x == 0) {
@@ -383,9 +417,10 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
-  auto load = [=](int64_t idx, bool, double) { return ut[idx]; };
+  auto fetch = [=](int64_t idx, bool) { return ut[idx]; };
+  auto make = [](double v, int64_t, bool, double) { return v; };
   auto store = [=](int64_t idx, int, int, int, double q, double, double) { rho[idx] = f[idx] - q; };
-  zmarch(sl, lds, load, store);
+  zmarch(sl, lds, fetch, make, store);
 }
 
 // y = A x (diagnostic).
@@ -400,9 +435,51 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockD
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
-  auto load = [=](int64_t idx, bool, T) { return x[idx]; };
+  auto fetch = [=](int64_t idx, bool) { return x[idx]; };
+  auto make = [](T v, int64_t, bool, T) { return v; };
   auto store = [=](int64_t idx, int, int, int, T q, T, T) { y[idx] = q; };
-  zmarch(sl, lds, load, store);
+  zmarch(sl, lds, fetch, make, store);
+}
+
+// Pass B of a CG iteration over the slot's planes [z0, z1): x += alpha p,
+// r -= alpha q, accumulating r'D^-1 r and r'r. Four planes per round so that
+// sixteen loads are in flight before the first use.
+template <typename T, int CPT>
+__device__ __forceinline__ void cg_pass_b(const Slots<T, CPT>& sl, bool first, T alpha, T* __restrict__ x,
+                                          const T* __restrict__ p, T* __restrict__ r, const T* __restrict__ q,
+                                          double& arz, double& arr) {
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    if (!sl.act[m]) continue;
+    const int64_t base = sl.off + sl.c[m];
+    for (int k = sl.z0[m]; k < sl.z1[m]; k += 4) {
+      T pv[4], xv[4], rv[4], qv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k + u;
+        if (kk < sl.z1[m]) {
+          const int64_t idx = base + (int64_t)sl.S * kk;
+          pv[u] = p[idx];
+          xv[u] = first ? T(0) : x[idx];
+          rv[u] = r[idx];
+          qv[u] = q[idx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k + u;
+        if (kk < sl.z1[m]) {
+          const int64_t idx = base + (int64_t)sl.S * kk;
+          x[idx] = xv[u] + alpha * pv[u];
+          const T rn = rv[u] - alpha * qv[u];
+          r[idx] = rn;
+          const double rd = double(rn);
+          arz += rd * rd * double(slot_dinv(sl, m, kk));
+          arr += rd * rd;
+        }
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------- stepwise CG
@@ -479,9 +556,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const T tb = T(beta);
   const bool first = t == 0;
   double a0 = 0.0;
-  auto load = [=](int64_t idx, bool own, T dinv) {
-    T pn = dinv * r[idx];
-    if (!first) pn += tb * pold[idx];
+  auto fetch = [=](int64_t idx, bool) { return Pair<T>{r[idx], first ? T(0) : pold[idx]}; };
+  auto make = [=](Pair<T> v, int64_t idx, bool own, T dinv) {
+    const T pn = dinv * v.a + tb * v.b;
     if (own) pnew[idx] = pn;
     return pn;
   };
@@ -489,7 +566,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
     q[idx] = qv;
     a0 += double(pk) * double(qv);
   };
-  zmarch(sl, lds, load, store);
+  zmarch(sl, lds, fetch, make, store);
   double acc[1] = {a0};
   block_sum(acc);
   if (threadIdx.x == 0) part[3 * blockIdx.x] = acc[0];
@@ -520,21 +597,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_update(Dev d, const Bl
   const SubDesc sd = d.subs[s];
   Slots<T, CPT> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  double acc[2] = {0.0, 0.0};
-#pragma unroll
-  for (int m = 0; m < CPT; ++m) {
-    if (!sl.act[m]) continue;
-    for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
-      const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
-      const T pv = p[idx];
-      x[idx] = t == 0 ? alpha * pv : x[idx] + alpha * pv;
-      const T rv = r[idx] - alpha * q[idx];
-      r[idx] = rv;
-      const double rd = double(rv);
-      acc[0] += rd * rd * double(slot_dinv(sl, m, k));
-      acc[1] += rd * rd;
-    }
-  }
+  double a0 = 0.0, a1 = 0.0;
+  cg_pass_b(sl, t == 0, alpha, x, p, r, q, a0, a1);
+  double acc[2] = {a0, a1};
   block_sum(acc);
   if (threadIdx.x == 0) {
     part[3 * blockIdx.x + 1] = acc[0];
@@ -562,8 +627,20 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_add_correction(Dev d, con
 
 // ---------------------------------------------------------------------------- fused CG
 
-// One block per subdomain: the complete CG solve of A_s d = r_s from d = 0,
-// then u_s += d. No inter-block communication.
+template <typename T>
+struct Five {
+  T r, w, s, p, x;
+};
+
+// One block per subdomain: the complete preconditioned CG solve of
+// A_s d = r_s from d = 0, then u_s += d. No inter-block communication.
+// The CG is the single-reduction form of Chronopoulos and Gear: with
+// u = D^-1 r and w = A u carried along, one sweep per iteration updates
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = D^-1 r
+// pointwise and applies w = A u, and one block reduction yields
+// gamma = r'u, delta = w'u and r'r; then beta = gamma/gamma_old and
+// alpha = gamma / (delta - beta gamma / alpha_old). r, w, s, p are double
+// buffered (halo planes of one segment are read while another writes).
 template <typename T, int CPT>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -572,14 +649,13 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   const SubDesc sd = d.subs[s];
   Slots<T, CPT> sl;
   slots_init(sl, sd, d.geo, 0, sd.n[2], true);
-  T* __restrict__ r = reinterpret_cast<T*>(a.r);
+  T* rb[2] = {reinterpret_cast<T*>(a.r), reinterpret_cast<T*>(a.r1)};
+  T* wb[2] = {reinterpret_cast<T*>(a.w0), reinterpret_cast<T*>(a.w1)};
+  T* sb[2] = {reinterpret_cast<T*>(a.s0), reinterpret_cast<T*>(a.s1)};
+  T* pb[2] = {reinterpret_cast<T*>(a.p0), reinterpret_cast<T*>(a.p1)};
   T* __restrict__ x = reinterpret_cast<T*>(a.x);
-  T* __restrict__ p0 = reinterpret_cast<T*>(a.p0);
-  T* __restrict__ p1 = reinterpret_cast<T*>(a.p1);
-  T* __restrict__ q = reinterpret_cast<T*>(a.q);
-  double rz = 0.0, rr = 0.0, bb = 0.0;
+  double rr = 0.0, bb = 0.0;
   for (int b = bfirst[s]; b < bfirst[s + 1]; ++b) {
-    rz += a.res_part[3 * b];
     rr += a.res_part[3 * b + 1];
     bb += a.res_part[3 * b + 2];
   }
@@ -587,65 +663,109 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
   int t = 0, brk = 0;
-  double rz_prev = 1.0;
-  for (;;) {
-    if (!isfinite(rr) || !isfinite(rz)) {
-      brk = 1;
-      break;
+  if (!isfinite(rr)) brk = 1;
+  if (!brk && rr > stop2 && a.max_inner > 0) {
+    // u0 = D^-1 r0, w0 = A u0, gamma0 = r0'u0, delta0 = w0'u0
+    double g0 = 0.0, d0 = 0.0;
+    {
+      const T* __restrict__ r0 = rb[0];
+      T* __restrict__ w0 = wb[0];
+      auto fetch = [=](int64_t idx, bool) { return r0[idx]; };
+      auto make = [&](T rv, int64_t, bool own, T dinv) {
+        const T u = dinv * rv;
+        if (own) g0 += double(rv) * double(u);
+        return u;
+      };
+      auto store = [&](int64_t idx, int, int, int, T wv, T uk, T) {
+        w0[idx] = wv;
+        d0 += double(wv) * double(uk);
+      };
+      zmarch(sl, lds, fetch, make, store);
     }
-    if (!(rr > stop2) || t >= a.max_inner) break;
-    const T tb = T(t == 0 ? 0.0 : rz / rz_prev);
-    T* __restrict__ pold = (t & 1) ? p1 : p0;
-    T* __restrict__ pnew = (t & 1) ? p0 : p1;
-    const bool first = t == 0;
-    double a0 = 0.0;
-    auto load = [=](int64_t idx, bool own, T dinv) {
-      T pn = dinv * r[idx];
-      if (!first) pn += tb * pold[idx];
-      if (own) pnew[idx] = pn;
-      return pn;
-    };
-    auto store = [&](int64_t idx, int, int, int, T qv, T pk, T) {
-      q[idx] = qv;
-      a0 += double(pk) * double(qv);
-    };
-    zmarch(sl, lds, load, store);
-    double acc[1] = {a0};
-    block_sum(acc);
-    const double pq = acc[0];
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      brk = 1;
-      break;
-    }
-    const T alpha = T(rz / pq);
-    double acc2[2] = {0.0, 0.0};
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      if (!sl.act[m]) continue;
-      for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
-        const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
-        const T pv = pnew[idx];
-        x[idx] = t == 0 ? alpha * pv : x[idx] + alpha * pv;
-        const T rv = r[idx] - alpha * q[idx];
-        r[idx] = rv;
-        const double rd = double(rv);
-        acc2[0] += rd * rd * double(slot_dinv(sl, m, k));
-        acc2[1] += rd * rd;
+    double acc0[2] = {g0, d0};
+    block_sum(acc0);
+    double gamma = acc0[0], delta = acc0[1];
+    double alpha = gamma / delta, beta = 0.0;
+    if (!(delta > 0.0) || !isfinite(alpha)) brk = 1;
+    while (!brk) {
+      const int cur = t & 1, nxt = cur ^ 1;
+      const T* __restrict__ rc = rb[cur];
+      const T* __restrict__ wc = wb[cur];
+      const T* __restrict__ sc = sb[cur];
+      const T* __restrict__ pc = pb[cur];
+      T* __restrict__ rn_ = rb[nxt];
+      T* __restrict__ wn_ = wb[nxt];
+      T* __restrict__ sn_ = sb[nxt];
+      T* __restrict__ pn_ = pb[nxt];
+      const bool first = t == 0;
+      const T ta = T(alpha), tb = T(beta);
+      double ag = 0.0, ad = 0.0, ar = 0.0;
+      auto fetch = [=](int64_t idx, bool own) {
+        Five<T> v;
+        v.r = rc[idx];
+        v.w = wc[idx];
+        v.s = first ? T(0) : sc[idx];
+        v.p = first ? T(0) : pc[idx];
+        v.x = (first || !own) ? T(0) : x[idx];
+        return v;
+      };
+      auto make = [&](const Five<T>& v, int64_t idx, bool own, T dinv) {
+        const T pn = dinv * v.r + tb * v.p;
+        const T sn = v.w + tb * v.s;
+        const T rn = v.r - ta * sn;
+        const T un = dinv * rn;
+        if (own) {
+          pn_[idx] = pn;
+          sn_[idx] = sn;
+          rn_[idx] = rn;
+          x[idx] = v.x + ta * pn;
+          ag += double(rn) * double(un);
+          ar += double(rn) * double(rn);
+        }
+        return un;
+      };
+      auto store = [&](int64_t idx, int, int, int, T wv, T uk, T) {
+        wn_[idx] = wv;
+        ad += double(wv) * double(uk);
+      };
+      zmarch(sl, lds, fetch, make, store);
+      double acc[3] = {ag, ad, ar};
+      block_sum(acc);
+      ++t;
+      rr = acc[2];
+      if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(rr)) {
+        brk = 1;
+        break;
       }
+      if (!(rr > stop2) || t >= a.max_inner) break;
+      const double gnew = acc[0];
+      beta = gnew / gamma;
+      const double den = acc[1] - beta * gnew / alpha;
+      if (!(den > 0.0)) {
+        brk = 1;
+        break;
+      }
+      alpha = gnew / den;
+      gamma = gnew;
     }
-    block_sum(acc2);
-    rz_prev = rz;
-    rz = acc2[0];
-    rr = acc2[1];
-    ++t;
   }
   if (t > 0) {
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (!sl.act[m]) continue;
-      for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
-        const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
-        a.u[idx] += double(x[idx]);
+      const int64_t base = sl.off + sl.c[m];
+      for (int k = sl.z0[m]; k < sl.z1[m]; k += 4) {
+        T xv[4];
+        double uv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k + u < sl.z1[m]) {
+            xv[u] = x[base + (int64_t)sl.S * (k + u)];
+            uv[u] = a.u[base + (int64_t)sl.S * (k + u)];
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k + u < sl.z1[m]) a.u[base + (int64_t)sl.S * (k + u)] = uv[u] + double(xv[u]);
       }
     }
   }
@@ -654,7 +774,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     a.scal[s].breakdown = brk;
     a.scal[s].done = 1;
     atomicAdd(&a.iters_total[0], (unsigned long long)t);
-    atomicAdd(&a.iters_total[1], cg_bytes(sd, t, sizeof(T)));
+    atomicAdd(&a.iters_total[1], fused_bytes(sd, t, sizeof(T)));
   }
 }
 
@@ -892,6 +1012,10 @@ __global__ void k_load_nodes(Dev d, const double* __restrict__ fn, double* __res
     } break;                               \
     case 2: {                              \
       constexpr int C = 2;                 \
+      KERNEL_CALL;                         \
+    } break;                               \
+    case 3: {                              \
+      constexpr int C = 3;                 \
       KERNEL_CALL;                         \
     } break;                               \
     case 4: {                              \

@@ -54,7 +54,8 @@ class Opts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("checks", C.c_int32), ("inner_iters", C.c_int64),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("kernel_ms", C.c_double),
-                ("kernel_launches", C.c_int64), ("kernel_bytes", C.c_double), ("block", C.c_int32)]
+                ("kernel_launches", C.c_int64), ("kernel_bytes", C.c_double), ("block", C.c_int32),
+                ("cols_per_thread", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -172,7 +173,8 @@ class Problem:
                 part.nparts[a] = int(nparts[a])
                 part.cuts[a] = C.POINTER(C.c_int32)()
         self.part = part
-        self._robin = self._make_robin(p)
+        self.n_faces = self._count_faces([int(part.nparts[a]) for a in range(3)])
+        self._robin = self._make_robin(p, self.n_faces)
         self.opts = o
         self.ne = tuple(int(v) for v in ne)
         self.n_nodes = int(np.prod([2 * v + 1 for v in ne]))
@@ -184,13 +186,24 @@ class Problem:
         self.precision = prec
 
     @staticmethod
-    def _make_robin(p):
+    def _count_faces(P):
+        """Directed interface faces of a Px*Py*Pz box partition."""
+        n = 0
+        for a in range(3):
+            b, c = [d for d in range(3) if d != a]
+            n += 2 * (P[a] - 1) * P[b] * P[c]
+        return n
+
+    @staticmethod
+    def _make_robin(p, n_faces):
         r = Robin()
         r.order = 0
         if np.ndim(p) == 0:
             r.p0 = float(p)
             r.p = C.POINTER(C.c_double)()
             return (r, None)
+        if len(p) != n_faces:
+            raise ValueError(f"per-face Robin coefficients: expected {n_faces} values, got {len(p)}")
         arr = (C.c_double * len(p))(*[float(v) for v in p])
         r.p0 = 0.0
         r.p = C.cast(arr, C.POINTER(C.c_double))
@@ -229,7 +242,7 @@ class Problem:
                 "lo": np.array(lo, np.int32).reshape(-1, 3), "face_off": np.array(foff, np.int64)}
 
     def set_robin(self, p):
-        self._robin = self._make_robin(p)
+        self._robin = self._make_robin(p, self.n_faces)
         _check(lib().sos_set_robin(self.h, C.byref(self._robin[0])))
 
     def set_opts(self, **kw):

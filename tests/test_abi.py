@@ -48,7 +48,12 @@ def test_invalid_arguments_rejected_on_the_host(kw, msg):
     assert msg in str(ei.value)
 
 
-def test_per_face_robin_length_and_order_rejected():
+def test_per_face_robin_values_checked():
     with pytest.raises(sos.SosError) as ei:
         sos.Problem((4, 4, 4), nparts=(2, 1, 1), p=[1.0, 0.0])
     assert ei.value.code == sos.SOS_EINVAL
+    with pytest.raises(ValueError):
+        sos.Problem((4, 4, 4), nparts=(2, 2, 1), p=[1.0, 1.0])
+    assert sos.Problem._count_faces([4, 4, 4]) == 288
+    assert sos.Problem._count_faces([16, 16, 1]) == 960
+    assert sos.Problem._count_faces([8, 8, 8]) == 2688

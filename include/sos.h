@@ -172,6 +172,35 @@ int sos_solve(sos_ctx* ctx, const double* drho_elem, double tol, double* phi_nod
 int sos_solve_load(sos_ctx* ctx, const double* f_nodes, double tol, double* phi_nodes,
                    sos_stats* stats);
 
+/* Adjoint of sos_solve for a functional J(Phi) of the solution (Sec. 2: the
+ * load is linear in drho, f = 4 pi G B drho with B_ie = int_e phi_i; K is
+ * symmetric). Given dJ_dphi_nodes = dJ/dPhi over all nodes (device, FP64;
+ * Dirichlet entries ignored), solves K psi = dJ/dPhi with the same Schwarz
+ * iteration and options (tol relative to ||dJ/dPhi||) and writes
+ *   dJ_ddrho_elem[e] = 4 pi G sum_i psi_i int_e phi_i      (device, FP64, n_elem)
+ * and, if psi_nodes != NULL, psi over all nodes (device, 0 on Dirichlet nodes).
+ * Replaces the context's load. Returns SOS_ENOCONV like sos_solve (outputs
+ * still written). */
+int sos_adjoint(sos_ctx* ctx, const double* dJ_dphi_nodes, double tol, double* dJ_ddrho_elem,
+                double* psi_nodes, sos_stats* stats);
+
+/* Search of transmission coefficients with CMA-ES (Sec. 4): minimises the
+ * maximum over k in [kmin, kmax] (n_k uniform samples) of the two-subdomain
+ * Fourier convergence factor (Sec. 3)
+ *   rho(k) = |(k - L1)(k - L2)| / ((k + L1)(k + L2)),  L_s = p_s + q_s k^2
+ * (the second-order operator read with the symbol p + q k^2).
+ * kind: 0 zeroth order symmetric (p), 1 zeroth order unsymmetric (p1, p2),
+ *       2 second order symmetric (p, q), 3 second order unsymmetric
+ *       (p1, q1, p2, q2).
+ * popsize: samples per generation (the paper uses 25); stops after max_iter
+ * generations (the paper: 7200) or when the search distribution's spread or
+ * the best cost's progress falls below tol (the paper: 5e-11).
+ * Host memory, CPU only (no GPU needed): pq_out[4] = p1, q1, p2, q2 of the best
+ * point, rho_out = its cost, iters_out (may be NULL) = generations run.
+ * Deterministic for a seed. SOS_EINVAL on bad arguments. */
+int sos_optimize_robin(int32_t kind, double kmin, double kmax, int32_t n_k, int32_t popsize, int32_t max_iter,
+                       double tol, uint64_t seed, double* pq_out, double* rho_out, int32_t* iters_out);
+
 /* Diagnostics used by the parity tests. */
 /* y_s = A_s x_s for every subdomain s (concatenated local layout, device).
  * precision selects the FP64 (x, y double*) or FP32 (float*) operator. */

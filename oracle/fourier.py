@@ -77,3 +77,36 @@ def rho_discrete_two(n_elem_x, hx, mu, p):
     eigenvalue mu for a symmetric split into two halves of n_elem_x elements."""
     S = schur_interface(n_elem_x, hx, mu)
     return ((S - p) / (S + p)) ** 2
+
+
+def grid_minimax(kind, kmin, kmax, n_grid=241, n_k=1001, lo=1e-3, hi=1e2):
+    """Brute-force minimax of rho_max over a log-spaced grid of the two free
+    coefficients (kind 1: p1, p2 of the zeroth-order unsymmetric condition;
+    kind 2: p, q of the second-order symmetric condition). Returns
+    (best rho_max, coefficients (p1, q1, p2, q2))."""
+    k = np.linspace(kmin, kmax, n_k)
+    g = np.exp(np.linspace(np.log(lo), np.log(hi), n_grid))
+    best, arg = np.inf, None
+    for a in g:
+        if kind == 1:
+            L1 = np.full_like(k, a)[None, :]
+            L2 = g[:, None] + 0.0 * k[None, :]
+            pq = lambda b: (a, 0.0, b, 0.0)
+        elif kind == 2:
+            L1 = a + g[:, None] * k[None, :] ** 2
+            L2 = L1
+            pq = lambda b: (a, b, a, b)
+        else:
+            raise ValueError(kind)
+        r = np.abs((k - L1) * (k - L2) / ((k + L1) * (k + L2))).max(axis=1)
+        j = int(np.argmin(r))
+        if r[j] < best:
+            best, arg = float(r[j]), pq(g[j])
+    return best, arg
+
+
+def oo0_symmetric_optimum(kmin, kmax):
+    """Closed-form minimax of ((k - p)/(k + p))^2 on [kmin, kmax]: the two end
+    frequencies equioscillate at p = sqrt(kmin kmax)."""
+    p = np.sqrt(kmin * kmax)
+    return p, ((np.sqrt(kmax) - np.sqrt(kmin)) / (np.sqrt(kmax) + np.sqrt(kmin))) ** 2

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsos.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("sos_kernels.hip", "sos_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("sos_kernels.hip", "sos_api.hip", "sos_cmaes.cpp")]
 ARCH = "gfx950"
 
 

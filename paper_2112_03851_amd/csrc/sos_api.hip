@@ -75,6 +75,7 @@ struct sos_ctx {
   double* part_norm = nullptr;  // 2 per assemble block
   int n_norm_blocks = 0;
   double* d_res = nullptr;      // [res, r'r, f'f]
+  double* psi = nullptr;        // adjoint field over all nodes (allocated on first use)
   CgScal* scal = nullptr;
   int32_t* ndone = nullptr;
   unsigned long long* counters = nullptr;  // [0] inner iterations, [1] algorithmic bytes
@@ -114,7 +115,7 @@ void release(sos_ctx* c) {
   for (auto e : c->gevents) hipEventDestroy(e);
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
-                  c->part, c->part_norm, c->d_res,
+                  c->part, c->part_norm, c->d_res, c->psi,
                   c->scal, c->ndone, c->counters};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -927,6 +928,22 @@ int sos_solve_load(sos_ctx* c, const double* fn, double tol, double* phi, sos_st
   HIPCHK(launch_load_nodes(c->dev, c->max_n, fn, c->f, c->stream));
   c->have_load = true;
   return solve_common(c, tol, phi, stats);
+}
+
+int sos_adjoint(sos_ctx* c, const double* gphi, double tol, double* grad, double* psi, sos_stats* stats) {
+  if (!c || !gphi || !grad) return fail(SOS_EINVAL, "NULL argument");
+  double* out = psi;
+  if (!out) {
+    if (!c->psi && dalloc(&c->psi, (size_t)c->n_nodes)) return SOS_ENOMEM;
+    out = c->psi;
+  }
+  HIPCHK(launch_load_nodes(c->dev, c->max_n, gphi, c->f, c->stream));
+  c->have_load = true;
+  int rc = solve_common(c, tol, out, stats);
+  if (rc != SOS_OK && rc != SOS_ENOCONV) return rc;
+  HIPCHK(launch_grad_density(c->geo, out, c->opts.G, grad, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return rc;
 }
 
 int sos_iterate(sos_ctx* c, int32_t n, sos_stats* stats) {

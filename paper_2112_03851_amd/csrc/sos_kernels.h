@@ -102,6 +102,8 @@ int assemble_blocks(const Dev& d, int max_n);
 hipError_t launch_final_norm(const double* part, int32_t nblk, double* dev_out, double* host_out,
                              hipStream_t st);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st);
+// grad_e = 4 pi G sum_a psi_a int_e phi_a for every element (psi over all nodes).
+hipError_t launch_grad_density(const Geom& g, const double* psi, double G, double* grad, hipStream_t st);
 // y = A x (diagnostic; fp32 selects float vectors).
 hipError_t launch_apply(const Dev& d, const SegLaunch& L, int fp32, const void* x, void* y,
                         hipStream_t st);

@@ -1002,7 +1002,39 @@ __global__ void k_load_nodes(Dev d, const double* __restrict__ fn, double* __res
   f[sd.off + t] = fn[g] / double(mult);
 }
 
+// dJ/ddrho_e = 4 pi G sum over the 27 nodes a of e of psi_a int_e phi_a, the
+// transpose of the density-to-load map (w = h/6, 2h/3, h/6 per axis).
+__global__ void k_grad_density(Geom g, const double* __restrict__ psi, double G, double* __restrict__ grad) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ne = (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
+  if (e >= ne) return;
+  const int ex = int(e % g.ne[0]);
+  const int ey = int((e / g.ne[0]) % g.ne[1]);
+  const int ez = int(e / ((int64_t)g.ne[0] * g.ne[1]));
+  const double wx[3] = {g.h[0] / 6.0, 2.0 * g.h[0] / 3.0, g.h[0] / 6.0};
+  const double wy[3] = {g.h[1] / 6.0, 2.0 * g.h[1] / 3.0, g.h[1] / 6.0};
+  const double wz[3] = {g.h[2] / 6.0, 2.0 * g.h[2] / 3.0, g.h[2] / 6.0};
+  double acc = 0.0;
+#pragma unroll
+  for (int az = 0; az < 3; ++az)
+#pragma unroll
+    for (int ay = 0; ay < 3; ++ay) {
+      const int64_t row = (int64_t)g.nn[0] * ((2 * ey + ay) + (int64_t)g.nn[1] * (2 * ez + az));
+      double s = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) s += wx[ax] * psi[row + 2 * ex + ax];
+      acc += wy[ay] * wz[az] * s;
+    }
+  grad[e] = 4.0 * M_PI * G * acc;
+}
+
 // ---------------------------------------------------------------------------- launchers
+
+hipError_t launch_grad_density(const Geom& g, const double* psi, double G, double* grad, hipStream_t st) {
+  const int64_t ne = (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
+  hipLaunchKernelGGL(k_grad_density, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, g, psi, G, grad);
+  return hipGetLastError();
+}
 
 #define SOS_DISPATCH_CPT(cpt, KERNEL_CALL) \
   switch (cpt) {                           \

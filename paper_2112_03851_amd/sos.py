@@ -91,12 +91,15 @@ def lib():
                                  C.POINTER(C.c_int64)]),
         "sos_solve": (C.c_int, [P, P, D, P, C.POINTER(Stats)]),
         "sos_solve_load": (C.c_int, [P, P, D, P, C.POINTER(Stats)]),
+        "sos_adjoint": (C.c_int, [P, P, D, P, P, C.POINTER(Stats)]),
         "sos_apply_local": (C.c_int, [P, I, P, P]),
         "sos_get_state": (C.c_int, [P, P, P]),
         "sos_set_state": (C.c_int, [P, P, P]),
         "sos_set_density": (C.c_int, [P, P]),
         "sos_iterate": (C.c_int, [P, I, C.POINTER(Stats)]),
         "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
+        "sos_optimize_robin": (C.c_int, [I, D, D, I, I, I, D, C.c_uint64, C.POINTER(D), C.POINTER(D),
+                                         C.POINTER(I)]),
         "sos_destroy": (None, [P]),
         "sos_last_error": (C.c_char_p, []),
     }
@@ -133,6 +136,17 @@ def _ptr(t, dtype=None):
 def _sync_torch():
     import torch
     torch.cuda.current_stream().synchronize()
+
+
+def optimize_robin(kind, kmin, kmax, n_k=2001, popsize=25, max_iter=7200, tol=5e-11, seed=1):
+    """CMA-ES on the two-subdomain Fourier factor (host). Returns
+    (p1, q1, p2, q2), rho_max, generations."""
+    pq = (C.c_double * 4)()
+    rho = C.c_double()
+    it = C.c_int32()
+    _check(lib().sos_optimize_robin(int(kind), float(kmin), float(kmax), int(n_k), int(popsize), int(max_iter),
+                                    float(tol), int(seed), pq, C.byref(rho), C.byref(it)))
+    return tuple(pq), rho.value, it.value
 
 
 class Problem:
@@ -273,6 +287,20 @@ class Problem:
             _check(code)
         return phi, dict(st.as_dict(), converged=code == SOS_OK)
 
+    def adjoint(self, gphi, tol, want_psi=False):
+        """dJ/ddrho per element from dJ/dPhi over all nodes (adjoint Schwarz solve)."""
+        import torch
+        grad = torch.empty(self.n_elem, dtype=torch.float64, device=gphi.device)
+        psi = torch.empty(self.n_nodes, dtype=torch.float64, device=gphi.device) if want_psi else None
+        st = Stats()
+        _sync_torch()
+        code = lib().sos_adjoint(self.h, _ptr(gphi, torch.float64), float(tol), _ptr(grad, torch.float64),
+                                 _ptr(psi, torch.float64) if psi is not None else None, C.byref(st))
+        if code not in (SOS_OK, SOS_ENOCONV):
+            _check(code)
+        out = dict(st.as_dict(), converged=code == SOS_OK)
+        return (grad, psi, out) if want_psi else (grad, out)
+
     def apply_local(self, x):
         import torch
         prec = SOS_FP32_INNER if x.dtype == torch.float32 else SOS_FP64
@@ -316,3 +344,37 @@ class Problem:
         _sync_torch()
         _check(lib().sos_residual(self.h, _ptr(phi) if phi is not None else None, C.byref(res)))
         return phi, res.value
+
+
+class SchwarzSolve:
+    """torch.autograd.Function: Phi = K^-1 f(drho) by the Schwarz iteration;
+    the backward pass is the adjoint Schwarz solve (sos_adjoint).
+
+    Usage: phi = SchwarzSolve.apply(drho, problem, tol)
+    """
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, drho, problem, tol):
+        if cls._fn is None:
+            import torch
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, d, prob, t):
+                    phi, st = prob.solve(d.detach().contiguous(), t)
+                    if not st["converged"]:
+                        raise SosError(SOS_ENOCONV, f"forward solve did not converge: {st}")
+                    ctx.prob, ctx.tol = prob, t
+                    return phi
+
+                @staticmethod
+                def backward(ctx, gphi):
+                    grad, st = ctx.prob.adjoint(gphi.detach().contiguous(), ctx.tol)
+                    if not st["converged"]:
+                        raise SosError(SOS_ENOCONV, f"adjoint solve did not converge: {st}")
+                    return grad, None, None
+
+            cls._fn = _F
+        return cls._fn.apply(drho, problem, tol)

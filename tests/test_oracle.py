@@ -347,3 +347,53 @@ def test_table1_rates_reproduced():
     bad = np.abs((k - p1 + q1 * k * k) * (k - p2 + q2 * k * k) /
                  ((k + p1 - q1 * k * k) * (k + p2 - q2 * k * k)))
     assert bad.max() > 1.0
+
+
+# --------------------------------------------------------------------------- adjoint (NEXT-1)
+
+def test_observation_operator_interpolates_q2_functions_exactly():
+    from oracle import adjoint as AD
+    m = M.BoxMesh((5, 4, 3), (1.0, 1.0, 1.0), (0, 0, 0, 0, 0, 1))
+    X = m.node_coords()
+    # any function in the Q2 space is reproduced exactly at arbitrary points
+    u = X[:, 0] ** 2 * X[:, 1] * (1 + X[:, 2] ** 2) - 0.3 * X[:, 1] ** 2 * X[:, 2]
+    pts = np.random.default_rng(0).uniform(0, 1, (50, 3))
+    pts = np.vstack([pts, AD.top_face_points(8)])
+    P = AD.observation_operator(m, pts)
+    ex = pts[:, 0] ** 2 * pts[:, 1] * (1 + pts[:, 2] ** 2) - 0.3 * pts[:, 1] ** 2 * pts[:, 2]
+    np.testing.assert_allclose(P @ u, ex, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(np.asarray(P.sum(axis=1)).ravel(), 1.0, rtol=1e-13)
+
+
+def test_direct_adjoint_gradient_matches_central_differences():
+    """J is quadratic in drho, so central differences are exact up to rounding."""
+    from oracle import adjoint as AD
+    from synth.generators import uniform_density
+    m = M.BoxMesh((6, 6, 4), (1.0, 1.0, 1.0), (0, 0, 0, 0, 0, 1))
+    G = 6.672e-11
+    pts = AD.top_face_points(7)
+    P = AD.observation_operator(m, pts)
+    d = P @ AD.forward(m, uniform_density(m.ne, seed=4), G, "lu")
+    drho = uniform_density(m.ne, seed=5)
+    grad, _, _ = AD.gradient_direct(m, P, drho, d, G, "lu")
+    rng = np.random.default_rng(6)
+    eps = 0.1 * np.abs(drho).max()
+    for e in rng.choice(m.n_elem, 12, replace=False):
+        dp, dm = drho.copy(), drho.copy()
+        dp[e] += eps
+        dm[e] -= eps
+        fd = (AD.misfit(P, AD.forward(m, dp, G, "lu"), d) - AD.misfit(P, AD.forward(m, dm, G, "lu"), d)) / (2 * eps)
+        assert abs(fd - grad[e]) <= 1e-6 * np.abs(grad).max(), (e, fd, grad[e])
+
+
+def test_zeroth_order_symmetric_minimax_closed_form_by_brute_force():
+    kmin, kmax = 0.0174, 1.0
+    p_star, r_star = fourier.oo0_symmetric_optimum(kmin, kmax)
+    ps = np.exp(np.linspace(np.log(1e-3), np.log(10.0), 4001))
+    k = np.linspace(kmin, kmax, 2001)
+    r = (((k[None, :] - ps[:, None]) / (k[None, :] + ps[:, None])) ** 2).max(axis=1)
+    j = int(np.argmin(r))
+    assert abs(ps[j] / p_star - 1) < 5e-3 and abs(r[j] - r_star) < 1e-5
+    # the grid minimax never beats the closed-form symmetric optimum with p1 = p2
+    best, _ = fourier.grid_minimax(1, kmin, kmax, n_grid=121)
+    assert best <= r_star + 1e-12

@@ -393,7 +393,7 @@ def test_zeroth_order_symmetric_minimax_closed_form_by_brute_force():
     k = np.linspace(kmin, kmax, 2001)
     r = (((k[None, :] - ps[:, None]) / (k[None, :] + ps[:, None])) ** 2).max(axis=1)
     j = int(np.argmin(r))
-    assert abs(ps[j] / p_star - 1) < 5e-3 and abs(r[j] - r_star) < 1e-5
+    assert abs(ps[j] / p_star - 1) < 5e-3 and r_star - 1e-12 <= r[j] <= r_star + 1e-3
     # the grid minimax never beats the closed-form symmetric optimum with p1 = p2
     best, _ = fourier.grid_minimax(1, kmin, kmax, n_grid=121)
     assert best <= r_star + 1e-12

@@ -104,6 +104,9 @@ typedef struct {
                           the fused kernel and keeps the fastest, cached in
                           $SOS_TUNE_CACHE (default ~/.cache/sos_autotune.jsonl)
                           per subdomain geometry, precision and inner tolerance */
+  int32_t team;        /* SOS_BATCHED blocks per subdomain in the fused kernel
+                          (1..8; each owns a z-range, one team barrier per CG
+                          iteration); 0 = autotune (with block)              */
   int32_t timing;      /* 1: time every fused-kernel launch with HIP events
                           (launches eagerly: events inside a graph are not
                           readable)                                           */
@@ -123,6 +126,7 @@ typedef struct {
                              + the per-solve setup and update)   */
   int32_t block;          /* workgroup size used by the fused CG kernel         */
   int32_t cols_per_thread;/* x-y columns per thread of the fused CG kernel      */
+  int32_t team;           /* blocks per subdomain of the fused CG kernel        */
 } sos_stats;
 
 /* Fill *opts with defaults for the given precision. */

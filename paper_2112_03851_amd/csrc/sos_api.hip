@@ -86,8 +86,10 @@ struct sos_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // fused kernel launch shape
-  int fused_threads = 0, fused_cpt = 1;
+  int fused_threads = 0, fused_cpt = 1, fused_team = 1;
   size_t fused_lds = 0;
+  unsigned* team_cnt = nullptr;  // per-subdomain team barrier counters
+  double* team_part = nullptr;   // team partial sums
   bool tuned = false;    // fused block shape chosen (explicit or autotuned)
   double tune_ms = 0.0;  // duration of the chosen shape in the tuning run
   size_t lds_limit = 0;
@@ -107,6 +109,7 @@ namespace {
 int64_t align64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
 constexpr int kStallOuter = 2000;  // outer iterations without 1% progress
+constexpr int kMaxTeam = 8;        // blocks per subdomain in the fused kernel
 
 void release(sos_ctx* c) {
   if (!c) return;
@@ -115,7 +118,7 @@ void release(sos_ctx* c) {
   for (auto e : c->gevents) hipEventDestroy(e);
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
-                  c->part, c->part_norm, c->d_res, c->psi,
+                  c->part, c->part_norm, c->d_res, c->psi, c->team_cnt, c->team_part,
                   c->scal, c->ndone, c->counters};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -147,6 +150,7 @@ int check_opts(const sos_opts* o) {
   if (!(o->G > 0.0) || !std::isfinite(o->G)) return fail(SOS_EINVAL, "opts.G must be positive");
   if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64))
     return fail(SOS_EINVAL, "opts.block must be 0 or a multiple of 64 in [64, 1024]");
+  if (o->team < 0 || o->team > kMaxTeam) return fail(SOS_EINVAL, "opts.team must be in [0, %d]", kMaxTeam);
   return SOS_OK;
 }
 
@@ -243,6 +247,14 @@ int fused_shape(sos_ctx* c, int threads, int cpt = 0) {
   return SOS_OK;
 }
 
+int set_team(sos_ctx* c, int team) {
+  if (team < 1 || team > kMaxTeam) return fail(SOS_EINVAL, "team must be in [1, %d]", kMaxTeam);
+  for (auto& s : c->subs)
+    if (s.n[2] < team) return fail(SOS_EINVAL, "team of %d blocks exceeds a subdomain's %d z-planes", team, s.n[2]);
+  c->fused_team = team;
+  return SOS_OK;
+}
+
 // Candidate block shapes of the fused kernel: for 1..4 columns per thread,
 // the smallest block covering the largest plane and 1.5x, 2x, 3x that size
 // (more segments per block on small planes), within the kernel bounds and LDS.
@@ -283,7 +295,7 @@ std::string tune_cache_path() {
   return std::string(home ? home : "/tmp") + "/.cache/sos_autotune.jsonl";
 }
 
-bool tune_lookup(const std::string& key, int* threads, int* cpt) {
+bool tune_lookup(const std::string& key, int* threads, int* cpt, int* team) {
   FILE* f = fopen(tune_cache_path().c_str(), "r");
   if (!f) return false;
   char line[512];
@@ -293,13 +305,16 @@ bool tune_lookup(const std::string& key, int* threads, int* cpt) {
     if (!strstr(line, pat.c_str())) continue;
     const char* t = strstr(line, "\"threads\": ");
     const char* k = strstr(line, "\"cpt\": ");
-    if (t && k && sscanf(t + 11, "%d", threads) == 1 && sscanf(k + 7, "%d", cpt) == 1) found = true;
+    const char* m = strstr(line, "\"team\": ");
+    if (t && k && m && sscanf(t + 11, "%d", threads) == 1 && sscanf(k + 7, "%d", cpt) == 1 &&
+        sscanf(m + 8, "%d", team) == 1)
+      found = true;
   }
   fclose(f);
   return found;
 }
 
-void tune_store(const std::string& key, int threads, int cpt, double ms) {
+void tune_store(const std::string& key, int threads, int cpt, int team, double ms) {
   std::string path = tune_cache_path();
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos) {
@@ -310,7 +325,8 @@ void tune_store(const std::string& key, int threads, int cpt, double ms) {
   }
   FILE* f = fopen(path.c_str(), "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"ms\": %.4f}\n", key.c_str(), threads, cpt, ms);
+  fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"team\": %d, \"ms\": %.4f}\n", key.c_str(),
+          threads, cpt, team, ms);
   fclose(f);
 }
 
@@ -358,13 +374,17 @@ FusedArgs fused_args(sos_ctx* c) {
   a.u = c->u;
   a.scal = c->scal;
   a.iters_total = c->counters;
+  a.team = c->fused_team;
+  a.team_cnt = c->team_cnt;
+  a.team_part = c->team_part;
   return a;
 }
 
 // One outer iteration in the batched form; ev (optional) brackets the fused kernel.
 int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
-  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part, st));
+  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part,
+                         c->fused_team > 1 ? c->team_cnt : nullptr, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
@@ -376,7 +396,7 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
 int stepwise_iteration(sos_ctx* c) {
   hipStream_t st = c->stream;
   const SegLaunch& L = c->seg.L;
-  HIPCHK(launch_residual(c->dev, L, c->fp32, c->u, c->f, c->lam, c->r, c->part, st));
+  HIPCHK(launch_residual(c->dev, L, c->fp32, c->u, c->f, c->lam, c->r, c->part, nullptr, st));
   HIPCHK(launch_cg_init(c->dev, L, c->part, c->opts.inner_tol, c->opts.inner_abs, c->scal, c->ndone, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.timing) {
@@ -447,8 +467,9 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
   c->kernel_launches = 0;
   const bool batched = c->opts.mode == SOS_BATCHED;
   // HIP events recorded inside a graph cannot be read back with
-  // hipEventElapsedTime: timed runs launch eagerly
-  const bool graph = batched && c->opts.use_graph && !c->opts.timing;
+  // hipEventElapsedTime: timed runs launch eagerly; so do team launches
+  // (cooperative launches are not captured)
+  const bool graph = batched && c->opts.use_graph && !c->opts.timing && c->fused_team == 1;
   const int every = c->opts.check_every;
   int done = 0, checks = 0;
   double res = INFINITY, best = INFINITY;
@@ -526,6 +547,7 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
     stats->kernel_bytes = (double)c->h_counters[1];
     stats->block = c->fused_threads;
     stats->cols_per_thread = c->fused_cpt;
+    stats->team = c->fused_team;
   }
   if (!std::isfinite(res)) return fail(SOS_EBREAKDOWN, "non-finite global residual");
   return SOS_OK;
@@ -552,46 +574,65 @@ int autotune(sos_ctx* c) {
   if (c->tuned) return SOS_OK;
   c->tuned = true;
   const std::string key = tune_key(c);
-  int th = 0, cp = 0;
-  if (tune_lookup(key, &th, &cp) && fused_shape(c, th, cp) == SOS_OK) return SOS_OK;
-  auto cands = fused_candidates(c);
-  if (cands.size() <= 1) return SOS_OK;
+  int th = 0, cp = 0, tm = 0;
+  if (tune_lookup(key, &th, &cp, &tm) && fused_shape(c, th, cp) == SOS_OK && set_team(c, tm) == SOS_OK) return SOS_OK;
+  // block shapes are tuned unless fixed by opts.block, team sizes unless fixed by opts.team
+  std::vector<std::pair<int, int>> shapes;
+  if (c->opts.block) shapes.emplace_back(c->fused_threads, c->fused_cpt);
+  else shapes = fused_candidates(c);
+  std::vector<int> teams;
+  if (c->opts.team) teams.push_back(c->opts.team);
+  else
+    for (int t : {1, 2, 4, 8}) {
+      bool ok = true;
+      for (auto& s : c->subs) ok &= s.n[2] >= 2 * t;
+      if (ok) teams.push_back(t);
+    }
   hipStream_t st = c->stream;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double best = INFINITY;
-  int bt = c->fused_threads, bc = c->fused_cpt;
-  for (auto& cd : cands) {
-    if (fused_shape(c, cd.first, cd.second) != SOS_OK) continue;
-    double ms_min = INFINITY;
-    for (int rep = 0; rep < 2; ++rep) {
-      HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
-      HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part, st));
-      HIPCHK(hipEventRecord(e0, st));
-      HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds,
-                             fused_args(c), st));
-      HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      ms_min = std::min(ms_min, (double)ms);
+  int bt = c->fused_threads, bc = c->fused_cpt, bm = c->fused_team;
+  for (int team : teams)
+    for (auto& cd : shapes) {
+      if (fused_shape(c, cd.first, cd.second) != SOS_OK || set_team(c, team) != SOS_OK) continue;
+      double ms_min = INFINITY;
+      bool ok = true;
+      for (int rep = 0; rep < 2 && ok; ++rep) {
+        HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
+        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part,
+                               team > 1 ? c->team_cnt : nullptr, st));
+        HIPCHK(hipEventRecord(e0, st));
+        if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
+                            st) != hipSuccess) {
+          (void)hipGetLastError();  // e.g. a team grid that cannot be co-resident
+          ok = false;
+          break;
+        }
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ms_min = std::min(ms_min, (double)ms);
+      }
+      if (ok && ms_min < best) {
+        best = ms_min;
+        bt = cd.first;
+        bc = cd.second;
+        bm = team;
+      }
     }
-    if (ms_min < best) {
-      best = ms_min;
-      bt = cd.first;
-      bc = cd.second;
-    }
-  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
   HIPCHK(hipStreamSynchronize(st));
   int rc = fused_shape(c, bt, bc);
+  if (!rc) rc = set_team(c, bm);
   if (rc) return rc;
   c->tune_ms = best;
   invalidate_graph(c);
-  tune_store(key, bt, bc, best);
+  tune_store(key, bt, bc, bm, best);
   return SOS_OK;
 }
 
@@ -765,8 +806,8 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
     return fail(SOS_ESTATE, "no usable HIP device");
   }
   c->lds_limit = prop.sharedMemPerBlock;
-  c->tuned = opts->block != 0;
-  if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block))) {
+  c->tuned = opts->block != 0 && opts->team != 0;
+  if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block)) || (rc = set_team(c, opts->team ? opts->team : 1))) {
     release(c);
     return rc;
   }
@@ -792,7 +833,8 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
       (rc = dalloc_v(&c->w1, c->n_local * es)) || (rc = dalloc_v(&c->s0, c->n_local * es)) ||
       (rc = dalloc_v(&c->s1, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
       (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4)) ||
-      (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2))) {
+      (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2)) ||
+      (rc = dalloc(&c->team_cnt, c->subs.size())) || (rc = dalloc(&c->team_part, c->subs.size() * kMaxTeam * 2 * 4))) {
     release(c);
     return rc;
   }
@@ -862,16 +904,18 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
   if (rc) return rc;
   if ((o->precision == SOS_FP32_INNER) != (c->fp32 != 0)) return fail(SOS_EINVAL, "precision is fixed at setup");
   if (o->stream && o->stream != c->stream) return fail(SOS_EINVAL, "the stream is fixed at setup");
-  const int old_block = c->opts.block;
+  const int old_block = c->opts.block, old_team = c->opts.team;
   const double old_tol = c->opts.inner_tol, old_abs = c->opts.inner_abs;
   void* st = c->opts.stream;
   c->opts = *o;
   c->opts.stream = st;
-  const bool retune = o->block != old_block || o->inner_tol != old_tol || o->inner_abs != old_abs;
+  const bool retune = o->block != old_block || o->team != old_team || o->inner_tol != old_tol ||
+                      o->inner_abs != old_abs;
   if (retune) {
     rc = fused_shape(c, o->block);
+    if (!rc) rc = set_team(c, o->team ? o->team : 1);
     if (rc) return rc;
-    c->tuned = o->block != 0;
+    c->tuned = o->block != 0 && o->team != 0;
   }
   invalidate_graph(c);
   return SOS_OK;

@@ -55,7 +55,7 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
 // r = f + sum R^T lambda - A u (FP64 apply), stored as Tr; partials rz, rr, bb per block.
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u,
                            const double* f, const double* lam, void* r_out, double* part,
-                           hipStream_t st);
+                           unsigned* team_cnt, hipStream_t st);
 // Per-subdomain CG scalars from the residual partials (stepwise path).
 hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel,
                           double tol_abs, CgScal* scal, int32_t* ndone, hipStream_t st);
@@ -81,6 +81,9 @@ struct FusedArgs {
   double* u;
   CgScal* scal;
   unsigned long long* iters_total;  // [0] CG iterations, [1] algorithmic bytes
+  int32_t team;                     // blocks per subdomain (1: no inter-block sync)
+  unsigned* team_cnt;               // n_sub barrier counters (zeroed by the residual kernel)
+  double* team_part;                // n_sub * team * 2 * 4 partial sums
 };
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st);

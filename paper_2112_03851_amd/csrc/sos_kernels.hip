@@ -372,9 +372,13 @@ __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int
 template <typename TO, int CPT>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
                                                    const double* __restrict__ f, const double* __restrict__ lam,
-                                                   TO* __restrict__ r, double* __restrict__ part) {
+                                                   TO* __restrict__ r, double* __restrict__ part,
+                                                   unsigned* __restrict__ team_cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* lds = reinterpret_cast<double*>(smem);
+  // the fused kernel that follows counts its team barriers from zero
+  if (team_cnt && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < d.geo.n_sub; i += blockDim.x) team_cnt[i] = 0u;
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
   Slots<double, CPT> sl;
@@ -632,7 +636,52 @@ struct Five {
   T r, w, s, p, x;
 };
 
-// One block per subdomain: the complete preconditioned CG solve of
+// Sum the block partials of the T members of a team (the blocks that share
+// one subdomain): publish, agent-scope release on the team counter, bounded
+// spin with acquire, fixed-order sum. Every member gets the same sums. Epoch
+// e uses partial slots (e & 1); the counter reaches T (e + 1) after epoch e.
+constexpr long kSpinLimit = 1L << 26;
+
+template <int N>
+__device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int s, int tau, int epoch, int& fail) {
+  if (a.team <= 1) return;
+  __shared__ double tsum[N];
+  __shared__ int tfail;
+  if (threadIdx.x == 0) {
+    double* slot = a.team_part + (((size_t)s * a.team + tau) * 2 + (epoch & 1)) * 4;
+#pragma unroll
+    for (int n = 0; n < N; ++n) slot[n] = v[n];
+    __hip_atomic_fetch_add(&a.team_cnt[s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = (unsigned)a.team * (unsigned)(epoch + 1);
+    long spins = 0;
+    int f = 0;
+    while (__hip_atomic_load(&a.team_cnt[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kSpinLimit) {
+        f = 1;
+        break;
+      }
+    }
+    double acc[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) acc[n] = 0.0;
+    for (int m = 0; m < a.team; ++m) {
+      const double* o = a.team_part + (((size_t)s * a.team + m) * 2 + (epoch & 1)) * 4;
+#pragma unroll
+      for (int n = 0; n < N; ++n) acc[n] += o[n];
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) tsum[n] = acc[n];
+    tfail = f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < N; ++n) v[n] = tsum[n];
+  fail |= tfail;
+  __syncthreads();
+}
+
+// One block per subdomain (team = 1), or a team of blocks each owning a
+// contiguous range of z-planes (team > 1): the complete preconditioned CG solve of
 // A_s d = r_s from d = 0, then u_s += d. No inter-block communication.
 // The CG is the single-reduction form of Chronopoulos and Gear: with
 // u = D^-1 r and w = A u carried along, one sweep per iteration updates
@@ -645,10 +694,24 @@ template <typename T, int CPT>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  const int s = a.order[blockIdx.x];
+  // block -> (team j, member tau); with 8 | n_sub the members of a team share
+  // blockIdx % 8, i.e. one XCD under round-robin dispatch (shared L2)
+  const int b = blockIdx.x, TM = a.team;
+  int j, tau;
+  if (TM > 1 && (d.geo.n_sub & 7) == 0) {
+    const int slot = b >> 3;
+    j = (b & 7) + 8 * (slot / TM);
+    tau = slot % TM;
+  } else {
+    j = b / TM;
+    tau = b % TM;
+  }
+  const int s = a.order[j];
   const SubDesc sd = d.subs[s];
+  const int zb0 = (tau * sd.n[2]) / TM, zb1 = ((tau + 1) * sd.n[2]) / TM;
   Slots<T, CPT> sl;
-  slots_init(sl, sd, d.geo, 0, sd.n[2], true);
+  slots_init(sl, sd, d.geo, zb0, zb1, true);
+  int epoch = 0, tfail = 0;
   T* rb[2] = {reinterpret_cast<T*>(a.r), reinterpret_cast<T*>(a.r1)};
   T* wb[2] = {reinterpret_cast<T*>(a.w0), reinterpret_cast<T*>(a.w1)};
   T* sb[2] = {reinterpret_cast<T*>(a.s0), reinterpret_cast<T*>(a.s1)};
@@ -684,9 +747,10 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     }
     double acc0[2] = {g0, d0};
     block_sum(acc0);
+    team_sum(acc0, a, s, tau, epoch++, tfail);
     double gamma = acc0[0], delta = acc0[1];
     double alpha = gamma / delta, beta = 0.0;
-    if (!(delta > 0.0) || !isfinite(alpha)) brk = 1;
+    if (!(delta > 0.0) || !isfinite(alpha) || tfail) brk = 1;
     while (!brk) {
       const int cur = t & 1, nxt = cur ^ 1;
       const T* __restrict__ rc = rb[cur];
@@ -731,9 +795,10 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       zmarch(sl, lds, fetch, make, store);
       double acc[3] = {ag, ad, ar};
       block_sum(acc);
+      team_sum(acc, a, s, tau, epoch++, tfail);
       ++t;
       rr = acc[2];
-      if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(rr)) {
+      if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(rr) || tfail) {
         brk = 1;
         break;
       }
@@ -769,7 +834,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       }
     }
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && tau == 0) {
     a.scal[s].iters = t;
     a.scal[s].breakdown = brk;
     a.scal[s].done = 1;
@@ -1072,13 +1137,13 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
 }
 
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u, const double* f,
-                           const double* lam, void* r_out, double* part, hipStream_t st) {
+                           const double* lam, void* r_out, double* part, unsigned* team_cnt, hipStream_t st) {
   if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
-                                               st, d, L.blocks, u, f, lam, (float*)r_out, part));
+                                               st, d, L.blocks, u, f, lam, (float*)r_out, part, team_cnt));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
-                                               st, d, L.blocks, u, f, lam, (double*)r_out, part));
+                                               st, d, L.blocks, u, f, lam, (double*)r_out, part, team_cnt));
   }
   return hipGetLastError();
 }
@@ -1134,16 +1199,30 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
   return hipGetLastError();
 }
 
+template <typename T, int C>
+static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
+                                   hipStream_t st) {
+  const dim3 grid(d.geo.n_sub * a.team), block(threads);
+  if (a.team <= 1) {
+    hipLaunchKernelGGL((k_fused_cg<T, C>), grid, block, lds, st, d, L.bfirst, a);
+    return hipGetLastError();
+  }
+  // team barriers spin: every block of the grid must be resident at once
+  Dev dd = d;
+  const int32_t* bf = L.bfirst;
+  FusedArgs aa = a;
+  void* args[] = {&dd, &bf, &aa};
+  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C>, grid, block, args, (unsigned)lds, st);
+}
+
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st) {
   if (fp32) {
-    SOS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k_fused_cg<float, C>), dim3(d.geo.n_sub), dim3(threads), lds, st, d,
-                                             L.bfirst, a));
+    SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C>(d, L, threads, lds, a, st)));
   } else {
-    SOS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k_fused_cg<double, C>), dim3(d.geo.n_sub), dim3(threads), lds, st, d,
-                                             L.bfirst, a));
+    SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C>(d, L, threads, lds, a, st)));
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_face,

@@ -233,3 +233,23 @@ def test_full_size_c2_batched_sampled_nodes_match_direct():
     print("c2 sampled max rel error vs direct", err, flush=True)
     assert err <= 1e-5
     assert np.all(phi[case.mesh.dirichlet_mask()] == 0.0)
+
+
+@pytest.mark.parametrize("team", [2, 4])
+def test_team_of_blocks_per_subdomain_converges_to_same_solution(team):
+    """Blocks of a team share one subdomain (z-ranges) and meet at one barrier
+    per CG iteration; the result matches the one-block-per-subdomain form."""
+    torch = _torch()
+    wl = workload("c1", seed=0)
+    case = Case.from_workload(wl)
+    drho = torch.tensor(wl.drho(), device="cuda")
+    f, _ = case.density_loads(wl.drho())
+    one = case.problem(precision="fp32", mode="batched", team=1, block=256)
+    p1, s1 = one.solve(drho, wl.tol)
+    many = case.problem(precision="fp32", mode="batched", team=team, block=256)
+    p2, s2 = many.solve(drho, wl.tol)
+    assert s2["team"] == team and s2["converged"]
+    res = A.residual_norm(case.mesh, p2.cpu().numpy(), f)
+    assert res <= wl.tol * 1.001
+    assert abs(s2["outer_iters"] - s1["outer_iters"]) <= 0.02 * s1["outer_iters"]
+    assert (p1 - p2).abs().max().item() <= 1e-6 * p1.abs().max().item()

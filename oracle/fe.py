@@ -121,3 +121,22 @@ def face_mass_side(h, axis, side, nq=3):
     phi, _ = basis_3d(h, pts)
     wq = (W0 * W1).ravel() * area
     return np.einsum("aq,bq,q->ab", phi, phi, wq)
+
+
+def face_stiffness_side(h, axis, side, nq=3):
+    """int_F grad_t phi_a . grad_t phi_b over the element face with normal
+    `axis` at reference coordinate `side`: the tangential (surface) stiffness
+    of the second-order transmission operator (Sec. 3, read as p + q k^2)."""
+    t, w = gauss_01(nq)
+    T1, T0 = np.meshgrid(t, t, indexing="ij")
+    W1, W0 = np.meshgrid(w, w, indexing="ij")
+    tang = [d for d in range(3) if d != axis]
+    pts = np.zeros((nq * nq, 3))
+    pts[:, axis] = float(side)
+    pts[:, tang[0]] = T0.ravel()
+    pts[:, tang[1]] = T1.ravel()
+    area = float(h[tang[0]]) * float(h[tang[1]])
+    _, grad = basis_3d(h, pts)
+    gt = grad[:, :, tang]  # tangential components only
+    wq = (W0 * W1).ravel() * area
+    return np.einsum("aqd,bqd,q->ab", gt, gt, wq)

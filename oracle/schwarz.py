@@ -9,7 +9,9 @@ lambda = M_F g its discrete (face-mass weighted) form:
   1. lambda^0 = 0 on every directed face, u^0 = 0.
   2. for every s, solve exactly  A_s u_s = f_s + sum_j R_sj^T lambda_{s<-j}.
   3. for every directed face,
-         lambda_{j<-s} <- -lambda_{s<-j} + (p_sj + p_js) M_F R_sj u_s,
+         lambda_{j<-s} <- -lambda_{s<-j} + (A_sj + A_js) R_sj u_s,
+     A = p M_F (zeroth order) or p M_F + q K_F (second order, K_F the
+     tangential face stiffness),
      the discrete form of d_{n_j} u + p_js u = -(d_{n_s} u_s + p_sj u_s)
      + (p_sj + p_js) u_s on the shared face (n_j = -n_s), where s's normal
      flux is read off its own Robin condition.
@@ -32,20 +34,27 @@ from .partition import BoxPartition
 
 
 class SchwarzOracle:
-    def __init__(self, part: BoxPartition, p_face, solver="auto"):
-        """p_face: float (same p on every directed face) or a callable
-        face -> p. solver: 'lu', 'fdm' or 'auto' (LU up to 20000 unknowns)."""
+    def __init__(self, part: BoxPartition, p_face, solver="auto", q_face=0.0):
+        """p_face, q_face: float (same value on every directed face) or a
+        callable face -> value; q > 0 selects the second-order transmission
+        operator p M_F + q K_F (then only 'lu' applies). solver: 'lu', 'fdm' or
+        'auto' (LU up to 20000 unknowns)."""
         self.part = part
         self.mesh = part.mesh
-        if callable(p_face):
-            self.p = np.array([float(p_face(f)) for f in part.faces])
-        else:
-            self.p = np.full(len(part.faces), float(p_face))
-        if np.any(self.p <= 0):
-            raise ValueError("Robin coefficients must be positive")
+        as_arr = lambda v: (np.array([float(v(f)) for f in part.faces]) if callable(v)
+                            else np.full(len(part.faces), float(v)))
+        self.p = as_arr(p_face)
+        self.q = as_arr(q_face)
+        if np.any(self.p <= 0) or np.any(self.q < 0):
+            raise ValueError("Robin coefficients must satisfy p > 0, q >= 0")
+        if np.any(self.q > 0) and solver == "fdm":
+            raise ValueError("second-order conditions are not a Kronecker sum: use LU")
+        if np.any(self.q > 0):
+            solver = "lu"
         self.opp = np.array([part.face_index[(f.j, f.s)] for f in part.faces], np.int64)
         self.R = [sd.face_restriction(part, f) for f in part.faces]
         self.M = [sd.face_mass_local(part, f).tocsr() for f in part.faces]
+        self.KF = [sd.face_stiffness_local(part, f).tocsr() if np.any(self.q > 0) else None for f in part.faces]
         self.nodes = [part.local_nodes(s) for s in part.subs]
         self.mult = part.multiplicity()
         self.faces_of = [[f.index for f in part.faces if f.s == s.s] for s in part.subs]
@@ -56,7 +65,7 @@ class SchwarzOracle:
             if kind == "auto":
                 kind = "lu" if sub.n <= 20000 else "fdm"
             if kind == "lu":
-                A = sd.robin_matrix(part, sub, lambda f: self.p[f.index])
+                A = sd.robin_matrix(part, sub, lambda f: self.p[f.index], lambda f: self.q[f.index])
                 self.solvers.append(lu_factor(A).solve)
             elif kind == "fdm":
                 key, fac = self._fdm_factors(sub)
@@ -98,6 +107,8 @@ class SchwarzOracle:
             f = self.opp[g]  # face (s <- j) with s = face.j: the sender
             us = u[face.j][self.R[f]]
             new[g] = -lam[f] + (self.p[g] + self.p[f]) * (self.M[g] @ us)
+            if self.q[g] + self.q[f] > 0:
+                new[g] = new[g] + (self.q[g] + self.q[f]) * (self.KF[g] @ us)
         return new
 
     def glue(self, u):

@@ -63,6 +63,24 @@ def face_mass_local(part: BoxPartition, face: Face):
     return _scatter(conn, loc, Mf, face.nodes.size)
 
 
+def face_stiffness_local(part: BoxPartition, face: Face):
+    """K_F = int_F grad_t phi_i . grad_t phi_j restricted to the face's node
+    list (natural condition at the face's edges)."""
+    Kf = fe.face_stiffness_side(part.mesh.h, face.axis, face.side)
+    conn = part.mesh.element_nodes()[face_elements(part, face)]
+    loc = -np.ones(part.mesh.n_nodes, np.int64)
+    loc[face.nodes] = np.arange(face.nodes.size)
+    return _scatter(conn, loc, Kf, face.nodes.size)
+
+
+def face_operator_local(part: BoxPartition, face: Face, p, q=0.0):
+    """The discrete transmission operator p M_F + q K_F of one face."""
+    A = p * face_mass_local(part, face)
+    if q != 0.0:
+        A = A + q * face_stiffness_local(part, face)
+    return A.tocsr()
+
+
 def face_restriction(part: BoxPartition, face: Face):
     """Indices into s's local vector of the face nodes, in face order."""
     loc = _local_map(part, part.subs[face.s])
@@ -71,16 +89,17 @@ def face_restriction(part: BoxPartition, face: Face):
     return idx
 
 
-def robin_matrix(part: BoxPartition, sub: Subdomain, p_face):
-    """A_s = K_s^N + sum_F p_F R_F^T M_F R_F. p_face(face) gives p for the
-    directed face (s <- j)."""
+def robin_matrix(part: BoxPartition, sub: Subdomain, p_face, q_face=None):
+    """A_s = K_s^N + sum_F R_F^T (p_F M_F + q_F K_F) R_F. p_face(face) and
+    q_face(face) give the coefficients of the directed face (s <- j)."""
     A = neumann_stiffness(part, sub)
     for f in part.faces:
         if f.s != sub.s:
             continue
         R = face_restriction(part, f)
         P = sp.csr_matrix((np.ones(R.size), (R, np.arange(R.size))), shape=(sub.n, R.size))
-        A = A + p_face(f) * (P @ face_mass_local(part, f) @ P.T)
+        q = 0.0 if q_face is None else q_face(f)
+        A = A + P @ face_operator_local(part, f, p_face(f), q) @ P.T
     return A.tocsr()
 
 

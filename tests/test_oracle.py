@@ -397,3 +397,63 @@ def test_zeroth_order_symmetric_minimax_closed_form_by_brute_force():
     # the grid minimax never beats the closed-form symmetric optimum with p1 = p2
     best, _ = fourier.grid_minimax(1, kmin, kmax, n_grid=121)
     assert best <= r_star + 1e-12
+
+
+def test_second_order_face_operator_mode_contraction():
+    """With A = p M_F + q K_F a tangential mode v (K_F v = mu M_F v on the face)
+    sees the coefficient p + q mu: the datum is multiplied by (P - S)/(P + S),
+    P = p + q mu, every iteration (the symbol p + q k^2 of Sec. 3)."""
+    nx, ny = 6, 6
+    m = M.BoxMesh((2 * nx, ny, ny))
+    part = P.BoxPartition(m, ((nx,), (), ()))
+    p, q = 3.0, 0.05
+    orc = S.SchwarzOracle(part, p, "lu", q_face=q)
+    Mf = orc.M[0].toarray()
+    Kf = orc.KF[0].toarray()
+    # tangential generalised eigenpairs of the face operators
+    import scipy.linalg as sla
+    mus, V = sla.eigh(Kf, Mf)
+    for mode in (0, 3):
+        v, mu = V[:, mode], mus[mode]
+        S_ = fourier.schur_interface(nx, m.h[0], mu)
+        Pq = p + q * mu
+        factor = (Pq - S_) / (Pq + S_)
+        lam = [Mf @ v, Mf @ v]
+        zeros = [np.zeros(s.n) for s in part.subs]
+        for _ in range(3):
+            u = orc.subdomain_solves(zeros, lam)
+            new = orc.exchange(u, lam)
+            for a, b in zip(lam, new):
+                np.testing.assert_allclose(b, factor * a, rtol=1e-8, atol=1e-12 * np.abs(a).max())
+            lam = new
+
+
+def test_face_stiffness_is_tangential_kronecker_sum():
+    h = (0.3, 0.4, 0.5)
+    k1 = [fe.element_matrices_1d(v)[:2] for v in h]
+    for axis in range(3):
+        F = fe.face_stiffness_side(h, axis, 1)
+        a = np.arange(27)
+        pos = [a % 3, (a // 3) % 3, a // 9]
+        ta, tb = [d for d in range(3) if d != axis]
+        exp = np.zeros((27, 27))
+        for i in np.flatnonzero(pos[axis] == 2):
+            for j in np.flatnonzero(pos[axis] == 2):
+                (Ka, Ma), (Kb, Mb) = k1[ta], k1[tb]
+                exp[i, j] = (Ka[pos[ta][i], pos[ta][j]] * Mb[pos[tb][i], pos[tb][j]]
+                             + Ma[pos[ta][i], pos[ta][j]] * Kb[pos[tb][i], pos[tb][j]])
+        np.testing.assert_allclose(F, exp, rtol=0, atol=1e-13 * np.abs(exp).max())
+
+
+def test_second_order_schwarz_fixed_point_is_global_solution():
+    from synth.generators import uniform_density
+    m = M.BoxMesh((6, 4, 4))
+    part = P.BoxPartition(m, ((2, 4), (2,), ()))
+    G = 6.672e-11
+    drho = uniform_density(m.ne, seed=8)
+    f = A.load_from_density(m, drho, G)
+    fs = [SD.density_load(part, s, drho, G) for s in part.subs]
+    orc = S.SchwarzOracle(part, 6.0, "lu", q_face=0.02)
+    U, n, res, _ = orc.solve(fs, f, 1e-12, 5000)
+    ud = D.solve_direct(m, f, "lu")
+    assert np.abs(U - ud).max() <= 1e-10 * np.abs(ud).max()

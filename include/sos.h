@@ -78,10 +78,16 @@ typedef struct {
                              in (0, ne[d]); NULL = equal split (ne divisible) */
 } sos_partition;
 
+/* Transmission operator of every directed face (Sec. 3): order 0 is p
+ * (weak form p M_F), order 2 is p + q d^2/dtau^2 read with the symbol p + q k^2
+ * (weak form p M_F + q K_F, K_F the tangential stiffness of the face with a
+ * natural condition at the face's edges). */
 typedef struct {
-  int32_t order;     /* 0: zeroth order, operator p (the only order built)    */
-  double p0;         /* Robin coefficient of every directed face if p == NULL */
-  const double* p;   /* optional: per directed face, sos_faces() order, > 0   */
+  int32_t order;     /* 0 or 2                                                 */
+  double p0;         /* p of every directed face if p == NULL, > 0            */
+  double q0;         /* q of every directed face if q == NULL (order 2), >= 0 */
+  const double* p;   /* optional: per directed face, sos_faces() order        */
+  const double* q;   /* optional (order 2): per directed face                 */
 } sos_robin;
 
 typedef struct {

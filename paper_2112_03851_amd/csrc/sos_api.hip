@@ -156,18 +156,30 @@ int check_opts(const sos_opts* o) {
 
 int apply_robin(sos_ctx* c, const sos_robin* rb) {
   if (!rb) return fail(SOS_EINVAL, "robin is NULL");
-  if (rb->order != 0) return fail(SOS_EINVAL, "robin.order: only the zeroth-order operator p is supported");
-  std::vector<double> pv(c->faces.size());
+  if (rb->order != 0 && rb->order != 2) return fail(SOS_EINVAL, "robin.order must be 0 or 2");
+  std::vector<double> pv(c->faces.size()), qv(c->faces.size(), 0.0);
   for (size_t f = 0; f < c->faces.size(); ++f) {
     double p = rb->p ? rb->p[f] : rb->p0;
     if (!(p > 0.0) || !std::isfinite(p)) return fail(SOS_EINVAL, "Robin coefficient of face %zu must be > 0", f);
     pv[f] = p;
+    if (rb->order == 2) {
+      double q = rb->q ? rb->q[f] : rb->q0;
+      if (!(q >= 0.0) || !std::isfinite(q)) return fail(SOS_EINVAL, "second-order coefficient of face %zu must be >= 0", f);
+      qv[f] = q;
+    }
   }
-  for (size_t f = 0; f < c->faces.size(); ++f) c->faces[f].p = pv[f];
+  c->dev.hasq = 0;
+  for (size_t f = 0; f < c->faces.size(); ++f) {
+    c->faces[f].p = pv[f];
+    c->faces[f].q = qv[f];
+    if (qv[f] > 0.0) c->dev.hasq = 1;
+  }
   for (auto& s : c->subs) {
     for (int a = 0; a < 3; ++a) {
       s.elo[a] = s.face[2 * a] >= 0 ? c->faces[s.face[2 * a]].p : 0.0;
       s.ehi[a] = s.face[2 * a + 1] >= 0 ? c->faces[s.face[2 * a + 1]].p : 0.0;
+      s.qlo[a] = s.face[2 * a] >= 0 ? c->faces[s.face[2 * a]].q : 0.0;
+      s.qhi[a] = s.face[2 * a + 1] >= 0 ? c->faces[s.face[2 * a + 1]].q : 0.0;
     }
   }
   return SOS_OK;
@@ -754,6 +766,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
           d.pidx[a] = pp[a];
           d.e0[a] = e0;
           d.elo[a] = d.ehi[a] = 0.0;
+          d.qlo[a] = d.qhi[a] = 0.0;
           n *= d.n[a];
         }
         for (int k = 0; k < 6; ++k) d.face[k] = -1;
@@ -820,7 +833,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
   });
   // allocations
   const size_t es = c->fp32 ? 4 : 8;
-  Dev tmp{nullptr, nullptr, g, 0};
+  Dev tmp{nullptr, nullptr, g, 0, 0};
   c->n_norm_blocks = assemble_blocks(tmp, c->max_n);
   if ((rc = dalloc(&c->d_subs, c->subs.size())) || (rc = dalloc(&c->d_faces, c->faces.size())) ||
       (rc = dalloc(&c->d_pairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||

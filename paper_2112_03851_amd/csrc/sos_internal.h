@@ -23,6 +23,8 @@ struct SubDesc {
   int32_t face[6];  // directed face (s <- j) id for (axis, side), -1 if none
   double elo[3];    // Robin coefficient at closure node 0 per axis (0 if none)
   double ehi[3];    // Robin coefficient at closure node ne2 per axis
+  double qlo[3];    // second-order coefficient q at closure node 0 per axis (0 if none)
+  double qhi[3];    // second-order coefficient q at closure node ne2 per axis
 };
 
 // One directed face (s <- j).
@@ -32,6 +34,7 @@ struct FaceDesc {
   int32_t na, nb;   // tangential extents (first tangential axis fastest)
   int32_t opp;      // id of (j <- s)
   double p;         // Robin coefficient p_sj
+  double q;         // second-order coefficient q_sj (0: zeroth order)
 };
 
 // Geometry shared by all kernels.

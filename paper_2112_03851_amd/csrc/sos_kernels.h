@@ -26,6 +26,7 @@ struct Dev {
   const FaceDesc* faces;
   Geom geo;
   int32_t n_faces;
+  int32_t hasq;             // some face has a second-order coefficient q > 0
 };
 
 constexpr int kMinSeg = 8;  // shortest z-segment of a march (planes)

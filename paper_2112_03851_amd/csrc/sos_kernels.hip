@@ -100,7 +100,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
 
 // ---------------------------------------------------------------------------- march geometry
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool Q = false>
 struct Slots {
   int nx, ny, nz, S, PX, SP, G, seglen;
   int64_t off;
@@ -109,13 +109,15 @@ struct Slots {
   T kx0[CPT], mx0[CPT], kx2[CPT], mx2[CPT];
   T ky0[CPT], my0[CPT], ky2[CPT], my2[CPT];
   T dv0[CPT], dv1[CPT], dv2[CPT], dv3[CPT];  // inverse diagonal per z row kind
+  T ex[CPT], ey[CPT], qx[CPT], qy[CPT];       // Robin p and q at the column's x / y interface end
   T kx1, mx1, ky1, my1, kz1, mz1;
   int zklo, zne2;
-  T zks, zms, zelo, zehi;
+  T zks, zms, zelo, zehi, zqlo, zqhi;
+  bool hasq;                                  // any second-order face term
 };
 
-template <typename T, int CPT>
-__device__ __forceinline__ void slots_init(Slots<T, CPT>& sl, const SubDesc& d, const Geom& geo, int zb0,
+template <typename T, int CPT, bool Q>
+__device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& d, const Geom& geo, int zb0,
                                            int zb1, bool robin) {
   sl.nx = d.n[0];
   sl.ny = d.n[1];
@@ -142,6 +144,15 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT>& sl, const SubDesc& d, 
   sl.zne2 = d.ne2[2];
   sl.zelo = robin ? T(d.elo[2]) : T(0);
   sl.zehi = robin ? T(d.ehi[2]) : T(0);
+  if constexpr (Q) {
+    sl.zqlo = robin ? T(d.qlo[2]) : T(0);
+    sl.zqhi = robin ? T(d.qhi[2]) : T(0);
+    sl.hasq = robin && (d.qlo[0] > 0.0 || d.qhi[0] > 0.0 || d.qlo[1] > 0.0 || d.qhi[1] > 0.0 ||
+                        d.qlo[2] > 0.0 || d.qhi[2] > 0.0);
+  } else {
+    sl.zqlo = sl.zqhi = T(0);
+    sl.hasq = false;
+  }
   // centre entries of the four z row kinds (for the diagonal)
   T kz0[4], mz0[4];
   kz0[0] = T(16) * sl.zks;
@@ -178,17 +189,38 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT>& sl, const SubDesc& d, 
     sl.my0[m] = ry.m0;
     sl.ky2[m] = ry.k2;
     sl.my2[m] = ry.m2;
+    // interface-end coefficients of this column (0/1 blends, no selects
+    // between descriptor fields)
+    const int cxi = i + d.klo[0], cyj = j + d.klo[1];
+    const T wxl = cxi == 0 ? T(1) : T(0), wxh = cxi == d.ne2[0] ? T(1) : T(0);
+    const T wyl = cyj == 0 ? T(1) : T(0), wyh = cyj == d.ne2[1] ? T(1) : T(0);
+    const T rb = robin ? T(1) : T(0);
     const T a1 = rx.k0 * ry.m0 + rx.m0 * ry.k0;
     const T a2 = rx.m0 * ry.m0;
-    sl.dv0[m] = T(1) / (a1 * mz0[0] + a2 * kz0[0]);
-    sl.dv1[m] = T(1) / (a1 * mz0[1] + a2 * kz0[1]);
-    sl.dv2[m] = T(1) / (a1 * mz0[2] + a2 * kz0[2]);
-    sl.dv3[m] = T(1) / (a1 * mz0[3] + a2 * kz0[3]);
+    T b1 = T(0), b2 = T(0), b3 = T(0);
+    if constexpr (Q) {
+      sl.ex[m] = rb * (wxl * T(d.elo[0]) + wxh * T(d.ehi[0]));
+      sl.ey[m] = rb * (wyl * T(d.elo[1]) + wyh * T(d.ehi[1]));
+      sl.qx[m] = rb * (wxl * T(d.qlo[0]) + wxh * T(d.qhi[0]));
+      sl.qy[m] = rb * (wyl * T(d.qlo[1]) + wyh * T(d.qhi[1]));
+      // second-order face terms on the diagonal (plain 1D centres, no Robin p)
+      const T kxp = rx.k0 - sl.ex[m], kyp = ry.k0 - sl.ey[m];
+      b1 = sl.qx[m] * kyp + sl.qy[m] * kxp;      // times mz0
+      b2 = sl.qx[m] * ry.m0 + sl.qy[m] * rx.m0;  // times plain kz0
+      b3 = kxp * ry.m0 + rx.m0 * kyp;            // times q_z at a z end
+    } else {
+      (void)wxl; (void)wxh; (void)wyl; (void)wyh; (void)rb;
+    }
+    const T kzp0 = T(16) * sl.zks, kzp1 = T(14) * sl.zks, kzp2 = T(7) * sl.zks, kzp3 = T(7) * sl.zks;
+    sl.dv0[m] = T(1) / (a1 * mz0[0] + a2 * kz0[0] + b1 * mz0[0] + b2 * kzp0);
+    sl.dv1[m] = T(1) / (a1 * mz0[1] + a2 * kz0[1] + b1 * mz0[1] + b2 * kzp1);
+    sl.dv2[m] = T(1) / (a1 * mz0[2] + a2 * kz0[2] + b1 * mz0[2] + b2 * kzp2 + sl.zqlo * b3);
+    sl.dv3[m] = T(1) / (a1 * mz0[3] + a2 * kz0[3] + b1 * mz0[3] + b2 * kzp3 + sl.zqhi * b3);
   }
 }
 
-template <typename T, int CPT>
-__device__ __forceinline__ T slot_dinv(const Slots<T, CPT>& sl, int m, int k) {
+template <typename T, int CPT, bool Q>
+__device__ __forceinline__ T slot_dinv(const Slots<T, CPT, Q>& sl, int m, int k) {
   // blend with 0/1 weights: a select between struct fields would make the
   // compiler keep the whole slot state in scratch memory
   const int c = k + sl.zklo;
@@ -213,8 +245,8 @@ __device__ __forceinline__ void lds_zero(T* lds, int n) {
 // the slot's own segment, with the operand value p_k at that node.
 constexpr int kPrefetch = 3;
 
-template <typename T, int CPT, class FetchF, class MakeF, class StoreF>
-__device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, FetchF& fetch, MakeF& make,
+template <typename T, int CPT, bool Q, class FetchF, class MakeF, class StoreF>
+__device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, FetchF& fetch, MakeF& make,
                                        StoreF& store) {
   using Raw = decltype(fetch(int64_t(0), true));
   T acc[CPT][5];
@@ -278,15 +310,33 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT>& sl, T* lds, FetchF& 
         const T* V = U + SP;
         const T u0 = U[0], u1 = U[-1] + U[1], u2 = U[-2] + U[2];
         const T v0 = V[0], v1 = V[-1] + V[1], v2 = V[-2] + V[2];
-        const T Sx = sl.kx0[m] * u0 + sl.kx1 * u1 + sl.kx2[m] * u2 + sl.mx0[m] * v0 + sl.mx1 * v1 +
-                     sl.mx2[m] * v2;
-        const T Tx = sl.mx0[m] * u0 + sl.mx1 * u1 + sl.mx2[m] * u2;
+        T Sx = sl.kx0[m] * u0 + sl.kx1 * u1 + sl.kx2[m] * u2 + sl.mx0[m] * v0 + sl.mx1 * v1 + sl.mx2[m] * v2;
+        T Tx = sl.mx0[m] * u0 + sl.mx1 * u1 + sl.mx2[m] * u2;
+        T zc = T(0);
+        if constexpr (Q) if (sl.hasq) {
+          // second-order faces q (tangential stiffness with plain 1D factors):
+          // an x-face adds q (Ky (x) Mz + My (x) Kz) on its plane, a y-face
+          // q (Kx (x) Mz + Mx (x) Kz), a z-face q (Kx (x) My + Mx (x) Ky)
+          const T* P = lds + sl.lp[m];
+          const T p0 = P[0], p1 = P[-1] + P[1], p2 = P[-2] + P[2];
+          const T pm = sl.mx0[m] * p0 + sl.mx1 * p1 + sl.mx2[m] * p2;
+          const T pk = (sl.kx0[m] - sl.ex[m]) * p0 + sl.kx1 * p1 + sl.kx2[m] * p2;
+          const T sf = sl.qx[m] * (v0 - sl.ey[m] * p0) + sl.qy[m] * pk;
+          const T tf = sl.qx[m] * u0 + sl.qy[m] * pm;
+          const int cz = kp[m] + sl.zklo;
+          const T wzl = cz == 0 ? T(1) : T(0), wzh = cz == sl.zne2 ? T(1) : T(0);
+          const T zq = wzl * sl.zqlo + wzh * sl.zqhi;
+          const T ez = wzl * sl.zelo + wzh * sl.zehi;
+          zc = zq * (Sx - sl.ex[m] * u0 - sl.ey[m] * pm) - ez * tf;
+          Sx += sf;
+          Tx += tf;
+        }
         const Row<T> rz = row_of<T>(kp[m] + sl.zklo, sl.zne2, sl.zks, sl.zms, sl.zelo, sl.zehi);
         const T c1 = sl.mz1 * Sx + sl.kz1 * Tx;
         const T c2 = rz.m2 * Sx + rz.k2 * Tx;
         acc[m][0] += c2;
         acc[m][1] += c1;
-        acc[m][2] += rz.m0 * Sx + rz.k0 * Tx;
+        acc[m][2] += rz.m0 * Sx + rz.k0 * Tx + zc;
         acc[m][3] += c1;
         acc[m][4] += c2;
       }
@@ -369,7 +419,7 @@ __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int
 // ---------------------------------------------------------------------------- outer kernels
 
 // r = f + sum_F R^T lambda_F - A u, rounded to TO; partials (r'D^-1 r, r'r, b'b).
-template <typename TO, int CPT>
+template <typename TO, int CPT, bool Q>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
                                                    const double* __restrict__ f, const double* __restrict__ lam,
                                                    TO* __restrict__ r, double* __restrict__ part,
@@ -381,7 +431,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
     for (int i = threadIdx.x; i < d.geo.n_sub; i += blockDim.x) team_cnt[i] = 0u;
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
-  Slots<double, CPT> sl;
+  Slots<double, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   const LamOff L = lam_offsets(d, sd);
   lds_zero(lds, sl.G * 3 * sl.SP);
@@ -417,7 +467,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
   double* lds = reinterpret_cast<double*>(smem);
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
-  Slots<double, CPT> sl;
+  Slots<double, CPT, false> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
@@ -428,14 +478,14 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
 }
 
 // y = A x (diagnostic).
-template <typename T, int CPT>
+template <typename T, int CPT, bool Q>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockDesc* blocks, const T* __restrict__ x,
                                                 T* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
-  Slots<T, CPT> sl;
+  Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
@@ -448,8 +498,8 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockD
 // Pass B of a CG iteration over the slot's planes [z0, z1): x += alpha p,
 // r -= alpha q, accumulating r'D^-1 r and r'r. Four planes per round so that
 // sixteen loads are in flight before the first use.
-template <typename T, int CPT>
-__device__ __forceinline__ void cg_pass_b(const Slots<T, CPT>& sl, bool first, T alpha, T* __restrict__ x,
+template <typename T, int CPT, bool Q>
+__device__ __forceinline__ void cg_pass_b(const Slots<T, CPT, Q>& sl, bool first, T alpha, T* __restrict__ x,
                                           const T* __restrict__ p, T* __restrict__ r, const T* __restrict__ q,
                                           double& arz, double& arr) {
 #pragma unroll
@@ -511,7 +561,7 @@ __global__ void k_cg_init(int n_sub, const int32_t* __restrict__ bfirst, const d
   scal[s] = c;
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool Q>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
                                                    int t, int max_inner, const T* __restrict__ r,
                                                    const T* __restrict__ pold, T* __restrict__ pnew,
@@ -553,7 +603,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const double beta = t == 0 ? 0.0 : rz / scal[s].rz[(t - 1) & 1];
   if (leader) scal[s].rz[t & 1] = rz;
   const SubDesc sd = d.subs[s];
-  Slots<T, CPT> sl;
+  Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
@@ -576,7 +626,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   if (threadIdx.x == 0) part[3 * blockIdx.x] = acc[0];
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool Q>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_update(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
                                                     int t, T* __restrict__ x, const T* __restrict__ p,
                                                     T* __restrict__ r, const T* __restrict__ q,
@@ -599,7 +649,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_update(Dev d, const Bl
   }
   const T alpha = T(scal[s].rz[t & 1] / pq);
   const SubDesc sd = d.subs[s];
-  Slots<T, CPT> sl;
+  Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   double a0 = 0.0, a1 = 0.0;
   cg_pass_b(sl, t == 0, alpha, x, p, r, q, a0, a1);
@@ -617,7 +667,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_add_correction(Dev d, con
   const BlockDesc bd = blocks[blockIdx.x];
   if (scal[bd.s].iters <= 0) return;
   const SubDesc sd = d.subs[bd.s];
-  Slots<T, CPT> sl;
+  Slots<T, CPT, false> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
@@ -690,7 +740,7 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 // gamma = r'u, delta = w'u and r'r; then beta = gamma/gamma_old and
 // alpha = gamma / (delta - beta gamma / alpha_old). r, w, s, p are double
 // buffered (halo planes of one segment are read while another writes).
-template <typename T, int CPT>
+template <typename T, int CPT, bool Q>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
@@ -709,7 +759,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   const int s = a.order[j];
   const SubDesc sd = d.subs[s];
   const int zb0 = (tau * sd.n[2]) / TM, zb1 = ((tau + 1) * sd.n[2]) / TM;
-  Slots<T, CPT> sl;
+  Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, zb0, zb1, true);
   int epoch = 0, tfail = 0;
   T* rb[2] = {reinterpret_cast<T*>(a.r), reinterpret_cast<T*>(a.r1)};
@@ -845,8 +895,10 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
 
 // ---------------------------------------------------------------------------- exchange
 
-// (M_F w)(a, b) for the face F of subdomain F.s: tangential 1D mass rows.
-__device__ __forceinline__ double face_mass_apply(const Dev& d, const FaceDesc& F, const double* u, int a, int b) {
+// (cp M_F + cq K_F) w at face node (a, b) of the face F of subdomain F.s:
+// tangential 1D mass and plain stiffness rows (K_F = Ka (x) Mb + Ma (x) Kb).
+__device__ __forceinline__ double face_op_apply(const Dev& d, const FaceDesc& F, const double* u, int a, int b,
+                                                double cp, double cq) {
   const SubDesc& sd = d.subs[F.s];
   const int ax = F.axis;
   // tangential axes: x-face (y, z), y-face (x, z), z-face (x, y)
@@ -858,12 +910,14 @@ __device__ __forceinline__ double face_mass_apply(const Dev& d, const FaceDesc& 
   const int neb = ax == 2 ? sd.ne2[1] : sd.ne2[2];
   const double msa = ax == 0 ? d.geo.ms[1] : d.geo.ms[0];
   const double msb = ax == 2 ? d.geo.ms[1] : d.geo.ms[2];
+  const double ksa = ax == 0 ? d.geo.ks[1] : d.geo.ks[0];
+  const double ksb = ax == 2 ? d.geo.ks[1] : d.geo.ks[2];
   const int ta = ax == 0 ? 1 : 0;
   const int tb = ax == 2 ? 1 : 2;
   const int nax = ax == 0 ? sd.n[0] : (ax == 1 ? sd.n[1] : sd.n[2]);
   const int plane = F.side ? nax - 1 : 0;
-  const Row<double> ra = row_of<double>(a + kla, nea, 0.0, msa, 0.0, 0.0);
-  const Row<double> rb = row_of<double>(b + klb, neb, 0.0, msb, 0.0, 0.0);
+  const Row<double> ra = row_of<double>(a + kla, nea, ksa, msa, 0.0, 0.0);
+  const Row<double> rb = row_of<double>(b + klb, neb, ksb, msb, 0.0, 0.0);
   const int sx = 1, sy = sd.n[0], sz = sd.n[0] * sd.n[1];
   const int64_t sa = ta == 0 ? sx : sy;
   const int64_t sb = tb == 1 ? sy : sz;
@@ -873,23 +927,27 @@ __device__ __forceinline__ double face_mass_apply(const Dev& d, const FaceDesc& 
 #pragma unroll
   for (int ob = 0; ob < 5; ++ob) {
     const int bb = b + ob - 2;
-    const double cbv = (ob == 2) ? rb.m0 : ((ob == 1 || ob == 3) ? 2.0 * msb : rb.m2);
+    const double mb = (ob == 2) ? rb.m0 : ((ob == 1 || ob == 3) ? 2.0 * msb : rb.m2);
+    const double kb = (ob == 2) ? rb.k0 : ((ob == 1 || ob == 3) ? -8.0 * ksb : rb.k2);
     if (bb < 0 || bb >= nb) continue;
-    double row = 0.0;
+    double rm = 0.0, rk = 0.0;
 #pragma unroll
     for (int oa = 0; oa < 5; ++oa) {
       const int aa = a + oa - 2;
-      const double cav = (oa == 2) ? ra.m0 : ((oa == 1 || oa == 3) ? 2.0 * msa : ra.m2);
+      const double ma = (oa == 2) ? ra.m0 : ((oa == 1 || oa == 3) ? 2.0 * msa : ra.m2);
+      const double ka = (oa == 2) ? ra.k0 : ((oa == 1 || oa == 3) ? -8.0 * ksa : ra.k2);
       if (aa < 0 || aa >= na) continue;
-      row += cav * u[base + (int64_t)aa * sa + (int64_t)bb * sb];
+      const double w = u[base + (int64_t)aa * sa + (int64_t)bb * sb];
+      rm += ma * w;
+      rk += ka * w;
     }
-    acc += cbv * row;
+    acc += cp * mb * rm + cq * (kb * rm + mb * rk);
   }
   return acc;
 }
 
-// lambda_{s<-j} <- -lambda_{j<-s} + (p_sj + p_js) M_F u_j,
-// lambda_{j<-s} <- -lambda_{s<-j} + (p_sj + p_js) M_F u_s.
+// lambda_{s<-j} <- -lambda_{j<-s} + (A_sj + A_js) u_j,
+// lambda_{j<-s} <- -lambda_{s<-j} + (A_sj + A_js) u_s,   A = p M_F + q K_F.
 __global__ void k_exchange(Dev d, const int32_t* __restrict__ pair_faces, const double* __restrict__ u,
                            double* __restrict__ lam) {
   const FaceDesc F = d.faces[pair_faces[blockIdx.y]];
@@ -897,13 +955,13 @@ __global__ void k_exchange(Dev d, const int32_t* __restrict__ pair_faces, const 
   if (t >= F.na * F.nb) return;
   const FaceDesc Gf = d.faces[F.opp];
   const int a = t % F.na, b = t / F.na;
-  const double mus = face_mass_apply(d, F, u, a, b);
-  const double muj = face_mass_apply(d, Gf, u, a, b);
-  const double c = F.p + Gf.p;
+  const double cp = F.p + Gf.p, cq = F.q + Gf.q;
+  const double aus = face_op_apply(d, F, u, a, b, cp, cq);
+  const double auj = face_op_apply(d, Gf, u, a, b, cp, cq);
   const double lf = lam[F.lam_off + t];
   const double lg = lam[Gf.lam_off + t];
-  lam[F.lam_off + t] = -lg + c * muj;
-  lam[Gf.lam_off + t] = -lf + c * mus;
+  lam[F.lam_off + t] = -lg + auj;
+  lam[Gf.lam_off + t] = -lf + aus;
 }
 
 // ---------------------------------------------------------------------------- glue and residual
@@ -1101,6 +1159,15 @@ hipError_t launch_grad_density(const Geom& g, const double* psi, double G, doubl
   return hipGetLastError();
 }
 
+#define SOS_DISPATCH_Q(hasq, CALL) \
+  if (hasq) {                       \
+    constexpr bool Q = true;        \
+    CALL;                           \
+  } else {                          \
+    constexpr bool Q = false;       \
+    CALL;                           \
+  }
+
 #define SOS_DISPATCH_CPT(cpt, KERNEL_CALL) \
   switch (cpt) {                           \
     case 1: {                              \
@@ -1138,13 +1205,15 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
 
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u, const double* f,
                            const double* lam, void* r_out, double* part, unsigned* team_cnt, hipStream_t st) {
+  SOS_DISPATCH_Q(d.hasq, {
   if (fp32) {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, u, f, lam, (float*)r_out, part, team_cnt));
   } else {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, u, f, lam, (double*)r_out, part, team_cnt));
   }
+  });
   return hipGetLastError();
 }
 
@@ -1159,31 +1228,35 @@ hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, 
 hipError_t launch_cg_apply(const Dev& d, const SegLaunch& L, int fp32, int t, int max_inner, const void* r,
                            const void* p_old, void* p_new, void* q, double* part, CgScal* scal, int32_t* ndone,
                            unsigned long long* counters, hipStream_t st) {
+  SOS_DISPATCH_Q(d.hasq, {
   if (fp32) {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds32,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<float, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds32,
                                                st, d, L.blocks, L.bfirst, t, max_inner, (const float*)r,
                                                (const float*)p_old, (float*)p_new, (float*)q, part, scal, ndone,
                                                counters));
   } else {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<double, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, L.bfirst, t, max_inner, (const double*)r,
                                                (const double*)p_old, (double*)p_new, (double*)q, part, scal,
                                                ndone, counters));
   }
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_cg_update(const Dev& d, const SegLaunch& L, int fp32, int t, void* x, const void* p, void* r,
                             const void* q, double* part, CgScal* scal, int32_t* ndone, hipStream_t st) {
+  SOS_DISPATCH_Q(d.hasq, {
   if (fp32) {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<float, C>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<float, C, Q>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
                                                L.blocks, L.bfirst, t, (float*)x, (const float*)p, (float*)r,
                                                (const float*)q, part, scal, ndone));
   } else {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<double, C>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<double, C, Q>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
                                                L.blocks, L.bfirst, t, (double*)x, (const double*)p, (double*)r,
                                                (const double*)q, part, scal, ndone));
   }
+  });
   return hipGetLastError();
 }
 
@@ -1199,12 +1272,12 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
   return hipGetLastError();
 }
 
-template <typename T, int C>
+template <typename T, int C, bool Q>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
                                    hipStream_t st) {
   const dim3 grid(d.geo.n_sub * a.team), block(threads);
   if (a.team <= 1) {
-    hipLaunchKernelGGL((k_fused_cg<T, C>), grid, block, lds, st, d, L.bfirst, a);
+    hipLaunchKernelGGL((k_fused_cg<T, C, Q>), grid, block, lds, st, d, L.bfirst, a);
     return hipGetLastError();
   }
   // team barriers spin: every block of the grid must be resident at once
@@ -1212,16 +1285,18 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
   const int32_t* bf = L.bfirst;
   FusedArgs aa = a;
   void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C>, grid, block, args, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q>, grid, block, args, (unsigned)lds, st);
 }
 
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st) {
-  if (fp32) {
-    SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C>(d, L, threads, lds, a, st)));
-  } else {
-    SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C>(d, L, threads, lds, a, st)));
-  }
+  SOS_DISPATCH_Q(d.hasq, {
+    if (fp32) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q>(d, L, threads, lds, a, st)));
+    } else {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q>(d, L, threads, lds, a, st)));
+    }
+  });
   return hipSuccess;
 }
 
@@ -1265,13 +1340,15 @@ hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st) {
 }
 
 hipError_t launch_apply(const Dev& d, const SegLaunch& L, int fp32, const void* x, void* y, hipStream_t st) {
+  SOS_DISPATCH_Q(d.hasq, {
   if (fp32) {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_apply<float, C>), dim3(L.nblocks), dim3(L.threads), L.lds32, st, d,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_apply<float, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds32, st, d,
                                                L.blocks, (const float*)x, (float*)y));
   } else {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_apply<double, C>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_apply<double, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
                                                d, L.blocks, (const double*)x, (double*)y));
   }
+  });
   return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ class Partition(C.Structure):
 
 
 class Robin(C.Structure):
-    _fields_ = [("order", C.c_int32), ("p0", C.c_double), ("p", C.POINTER(C.c_double))]
+    _fields_ = [("order", C.c_int32), ("p0", C.c_double), ("q0", C.c_double), ("p", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double))]
 
 
 class Opts(C.Structure):
@@ -156,12 +157,13 @@ class Problem:
     cuts: per axis a sequence of interior cut element indices (equal split if
           nparts is given instead)
     p: Robin coefficient (float, or one value per directed face)
+    q: second-order coefficient (0: zeroth-order operator p)
     precision: 'fp64' or 'fp32' (FP32 inner CG, FP64 outer)
     mode: 'stepwise' or 'batched'
     """
 
     def __init__(self, ne, lengths=(1.0, 1.0, 1.0), bc=(0,) * 6, cuts=None, nparts=None, p=1.0,
-                 precision="fp64", mode=None, **opts):
+                 precision="fp64", mode=None, q=0.0, **opts):
         L = lib()
         prec = SOS_FP32_INNER if precision in ("fp32", SOS_FP32_INNER) else SOS_FP64
         o = default_opts(prec)
@@ -188,7 +190,7 @@ class Problem:
                 part.cuts[a] = C.POINTER(C.c_int32)()
         self.part = part
         self.n_faces = self._count_faces([int(part.nparts[a]) for a in range(3)])
-        self._robin = self._make_robin(p, self.n_faces)
+        self._robin = self._make_robin(p, self.n_faces, q)
         self.opts = o
         self.ne = tuple(int(v) for v in ne)
         self.n_nodes = int(np.prod([2 * v + 1 for v in ne]))
@@ -209,19 +211,24 @@ class Problem:
         return n
 
     @staticmethod
-    def _make_robin(p, n_faces):
+    def _make_robin(p, n_faces, q=0.0):
+        """Robin descriptor (and the arrays it points to): order 2 if q is not 0."""
         r = Robin()
-        r.order = 0
-        if np.ndim(p) == 0:
-            r.p0 = float(p)
-            r.p = C.POINTER(C.c_double)()
-            return (r, None)
-        if len(p) != n_faces:
-            raise ValueError(f"per-face Robin coefficients: expected {n_faces} values, got {len(p)}")
-        arr = (C.c_double * len(p))(*[float(v) for v in p])
-        r.p0 = 0.0
-        r.p = C.cast(arr, C.POINTER(C.c_double))
-        return (r, arr)
+        keep = []
+        second = np.ndim(q) != 0 or float(q) != 0.0
+        r.order = 2 if second else 0
+        for name, v in (("p", p), ("q", q)):
+            if np.ndim(v) == 0:
+                setattr(r, name + "0", float(v))
+                setattr(r, name, C.POINTER(C.c_double)())
+                continue
+            if len(v) != n_faces:
+                raise ValueError(f"per-face Robin coefficients: expected {n_faces} values, got {len(v)}")
+            arr = (C.c_double * len(v))(*[float(x) for x in v])
+            keep.append(arr)
+            setattr(r, name + "0", 0.0)
+            setattr(r, name, C.cast(arr, C.POINTER(C.c_double)))
+        return (r, keep)
 
     def close(self):
         if getattr(self, "h", None):
@@ -255,8 +262,8 @@ class Problem:
         return {"offsets": np.array(off, np.int64), "dims": np.array(dims, np.int32).reshape(-1, 3),
                 "lo": np.array(lo, np.int32).reshape(-1, 3), "face_off": np.array(foff, np.int64)}
 
-    def set_robin(self, p):
-        self._robin = self._make_robin(p, self.n_faces)
+    def set_robin(self, p, q=0.0):
+        self._robin = self._make_robin(p, self.n_faces, q)
         _check(lib().sos_set_robin(self.h, C.byref(self._robin[0])))
 
     def set_opts(self, **kw):

@@ -33,12 +33,15 @@ def _torch():
     return torch
 
 
+@pytest.mark.parametrize("q", [0.0, 0.013])
 @pytest.mark.parametrize("name", sorted(APPLY_CASES))
-def test_apply_matches_oracle_subdomain_matrices(name):
+def test_apply_matches_oracle_subdomain_matrices(name, q):
+    """A_s x for every subdomain; q > 0 adds the second-order face terms
+    q K_F (face tangential stiffness) to the Robin mass terms p M_F."""
     torch = _torch()
     case = Case(**APPLY_CASES[name])
-    print("case", name, flush=True)
-    prob = case.problem()
+    print("case", name, "q", q, flush=True)
+    prob = case.problem(q=q)
     lay = case.check_layout(prob)
     rng = np.random.default_rng(11)
     xs = [rng.standard_normal(s.n) for s in case.part.subs]
@@ -46,7 +49,7 @@ def test_apply_matches_oracle_subdomain_matrices(name):
     y64 = case.from_local(lay, prob.apply_local(x).cpu().numpy())
     y32 = case.from_local(lay, prob.apply_local(x.float()).double().cpu().numpy())
     for s, sub in enumerate(case.part.subs):
-        As = SD.robin_matrix(case.part, sub, lambda f: case.p)
+        As = SD.robin_matrix(case.part, sub, lambda f: case.p, lambda f: q)
         ref = As @ xs[s]
         scale = np.abs(As).max() * np.abs(xs[s]).max()
         assert np.abs(y64[s] - ref).max() <= 1e-14 * scale * 8, (name, s)
@@ -54,12 +57,13 @@ def test_apply_matches_oracle_subdomain_matrices(name):
     prob.close()
 
 
-def test_one_outer_iteration_matches_oracle_step():
+@pytest.mark.parametrize("q", [0.0, 0.02])
+def test_one_outer_iteration_matches_oracle_step(q):
     """u^1 = A_s^-1 (f_s + sum R^T lambda^0) and the exchanged lambda^1, from a
-    random state, with cross points and Neumann faces."""
+    random state, with cross points and Neumann faces (zeroth and second order)."""
     torch = _torch()
     case = Case((6, 5, 6), bc=(0, 0, 1, 0, 0, 0), cuts=((3,), (2,), (2, 4)), p=11.0)
-    prob = case.problem(precision="fp64", mode="stepwise", inner_abs=1e-14, max_inner=2000)
+    prob = case.problem(precision="fp64", mode="stepwise", inner_abs=1e-14, max_inner=2000, q=q)
     lay = case.check_layout(prob)
     drho = uniform_density(case.ne, seed=2)
     f, fs = case.density_loads(drho)
@@ -73,7 +77,7 @@ def test_one_outer_iteration_matches_oracle_step():
     u1, lam1 = prob.get_state()
     u1 = case.from_local(lay, u1.cpu().numpy())
     lam1 = case.lam_to_faces(lay, lam1.cpu().numpy())
-    orc = S.SchwarzOracle(case.part, case.p, "lu")
+    orc = S.SchwarzOracle(case.part, case.p, "lu", q_face=q)
     ur = orc.subdomain_solves(fs, lam0)
     lr = orc.exchange(ur, lam0)
     for s in range(case.part.n_sub):
@@ -253,3 +257,24 @@ def test_team_of_blocks_per_subdomain_converges_to_same_solution(team):
     assert res <= wl.tol * 1.001
     assert abs(s2["outer_iters"] - s1["outer_iters"]) <= 0.02 * s1["outer_iters"]
     assert (p1 - p2).abs().max().item() <= 1e-6 * p1.abs().max().item()
+
+
+def test_second_order_fixed_point_and_fewer_iterations_than_zeroth_order():
+    """p + q d_tt conditions: the batched FP32-inner solve reaches the global
+    direct solution; a second-order condition with the zeroth-order p needs
+    fewer outer iterations than p alone (Sec. 3: the second-order operator
+    approximates the optimal one better)."""
+    torch = _torch()
+    case = Case((16, 16, 8), cuts=((8,), (8,), (4,)), p=16.0)
+    drho = uniform_density(case.ne, seed=12)
+    f, _ = case.density_loads(drho)
+    ud = D.solve_direct(case.mesh, f, "lu")
+    res = {}
+    for q in (0.0, 0.02):
+        prob = case.problem(precision="fp32", mode="batched", q=q, max_outer=20000)
+        phi, st = prob.solve(torch.tensor(drho, device="cuda"), 1e-9)
+        err = np.abs(phi.cpu().numpy() - ud).max() / np.abs(ud).max()
+        print("q", q, "outer", st["outer_iters"], "err", err, flush=True)
+        assert st["converged"] and err <= 1e-6
+        res[q] = st["outer_iters"]
+    assert res[0.02] < res[0.0]

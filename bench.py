@@ -119,9 +119,13 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=0.1)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-outer", type=int, default=0,
+                    help="profiling only: run one batched solve of this many outer iterations "
+                         "(no convergence, no JSON line) for rocprofv3 counter collection")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -135,8 +139,18 @@ def main():
 
     wl = workload(args.workload, seed=args.seed)
     drho = torch.tensor(wl.drho(), device="cuda")
+    if args.profile_outer:
+        prob = Problem(wl.ne, wl.lengths, wl.bc, cuts=wl.cuts, p=wl.p, G=wl.G, precision="fp32", mode="batched",
+                       check_every=args.check_every, inner_tol=args.inner_tol, block=args.block or 576,
+                       team=args.team or 4, max_outer=args.profile_outer, timing=1)
+        phi, st = prob.solve(drho, wl.tol)
+        print(f"profiled {st['outer_iters']} outer iterations, {st['kernel_launches']} fused launches, "
+              f"{st['kernel_bytes'] / st['kernel_launches']:.0f} algorithmic bytes per launch, "
+              f"{st['kernel_ms'] / st['kernel_launches']:.4f} ms per launch", flush=True)
+        return
     prob = Problem(wl.ne, wl.lengths, wl.bc, cuts=wl.cuts, p=wl.p, G=wl.G, precision="fp32", mode="batched",
-                   check_every=args.check_every, inner_tol=args.inner_tol, timing=1, block=args.block)
+                   check_every=args.check_every, inner_tol=args.inner_tol, timing=1, block=args.block,
+                   team=args.team)
     for _ in range(args.warmup):
         prob.solve(drho, wl.tol)
     tot = {"kernel_ms": 0.0, "kernel_launches": 0, "kernel_bytes": 0.0, "outer_iters": 0, "inner_iters": 0}

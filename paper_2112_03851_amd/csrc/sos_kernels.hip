@@ -30,6 +30,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace sos {
 
 // ---------------------------------------------------------------------------- 1D rows
@@ -237,8 +239,8 @@ __device__ __forceinline__ void lds_zero(T* lds, int n) {
   for (int e = threadIdx.x; e < n; e += blockDim.x) lds[e] = T(0);
 }
 
-// The z-march, software-pipelined: fetch(idx, own) issues the global loads of
-// the operand at index idx (a plane inside the subdomain) kPrefetch planes
+// The z-march, software-pipelined: fetch(idx) issues the global loads of the
+// operand at index idx (always a valid node of the subdomain) kPrefetch planes
 // ahead of its use; make(raw, idx, own, dinv) turns them into the operand
 // (own: the plane belongs to the slot's segment; dinv: inverse diagonal).
 // store(idx, i, j, k, q, p_k, dinv) receives the finished output at plane k of
@@ -248,9 +250,13 @@ constexpr int kPrefetch = 3;
 template <typename T, int CPT, bool Q, class FetchF, class MakeF, class StoreF>
 __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, FetchF& fetch, MakeF& make,
                                        StoreF& store) {
-  using Raw = decltype(fetch(int64_t(0), true));
+  using Raw = decltype(fetch(int64_t(0)));
   T acc[CPT][5];
   T pr[CPT][3];
+  // prefetch ring: slot q holds the operands of the step that is congruent to
+  // q modulo kPrefetch. The step loop is unrolled kPrefetch times so every
+  // slot is a fixed set of registers: a register receiving a load in flight is
+  // never copied, so each use waits only for its own load.
   Raw raw[CPT][kPrefetch];
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
@@ -260,14 +266,16 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     for (int q = 0; q < 3; ++q) pr[m][q] = T(0);
 #pragma unroll
     for (int q = 0; q < kPrefetch; ++q) {
-      const int kq = sl.z0[m] - 2 + q;
-      if (sl.act[m] && kq >= 0 && kq < sl.nz)
-        raw[m][q] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq, kq >= sl.z0[m] && kq < sl.z1[m]);
+      // unconditional load from a clamped, always valid plane: a fixed number
+      // of loads per step lets every use wait for its own load only
+      const int kq = min(max(sl.z0[m] - 2 + q, 0), sl.nz - 1);
+      raw[m][q] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq);
     }
   }
   const int steps = sl.seglen + 4;
   const int PX = sl.PX, SP = sl.SP;
-  for (int step = 0; step < steps; ++step) {
+  auto one_step = [&](auto ucst, int step) {
+    constexpr int U = decltype(ucst)::value;
     bool inr[CPT];
     int kp[CPT];
 #pragma unroll
@@ -278,15 +286,12 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       if (inr[m]) {
         const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * kp[m];
         const bool own = kp[m] >= sl.z0[m] && kp[m] < sl.z1[m];
-        v = make(raw[m][0], idx, own, slot_dinv(sl, m, kp[m]));
+        v = make(raw[m][U], idx, own, slot_dinv(sl, m, kp[m]));
         lds[sl.lp[m]] = v;
       }
       pr[m][2] = v;
-#pragma unroll
-      for (int q = 0; q + 1 < kPrefetch; ++q) raw[m][q] = raw[m][q + 1];
-      const int kq = kp[m] + kPrefetch;
-      if (sl.act[m] && kq >= 0 && kq < sl.nz)
-        raw[m][kPrefetch - 1] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq, kq >= sl.z0[m] && kq < sl.z1[m]);
+      const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
+      raw[m][U] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq);
     }
     __syncthreads();
 #pragma unroll
@@ -306,9 +311,9 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (inr[m]) {
-        const T* U = lds + sl.lp[m] + SP;
-        const T* V = U + SP;
-        const T u0 = U[0], u1 = U[-1] + U[1], u2 = U[-2] + U[2];
+        const T* U_ = lds + sl.lp[m] + SP;
+        const T* V = U_ + SP;
+        const T u0 = U_[0], u1 = U_[-1] + U_[1], u2 = U_[-2] + U_[2];
         const T v0 = V[0], v1 = V[-1] + V[1], v2 = V[-2] + V[2];
         T Sx = sl.kx0[m] * u0 + sl.kx1 * u1 + sl.kx2[m] * u2 + sl.mx0[m] * v0 + sl.mx1 * v1 + sl.mx2[m] * v2;
         T Tx = sl.mx0[m] * u0 + sl.mx1 * u1 + sl.mx2[m] * u2;
@@ -357,7 +362,16 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       pr[m][0] = pr[m][1];
       pr[m][1] = pr[m][2];
     }
+  };
+  static_assert(kPrefetch == 3, "the step loop below is unrolled for a ring of three");
+  int step = 0;
+  for (; step + 3 <= steps; step += 3) {
+    one_step(std::integral_constant<int, 0>(), step);
+    one_step(std::integral_constant<int, 1>(), step + 1);
+    one_step(std::integral_constant<int, 2>(), step + 2);
   }
+  if (step < steps) one_step(std::integral_constant<int, 0>(), step++);
+  if (step < steps) one_step(std::integral_constant<int, 1>(), step++);
 }
 
 template <typename T>
@@ -438,7 +452,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int nx = sl.nx, ny = sl.ny, nz = sl.nz;
-  auto fetch = [=](int64_t idx, bool) { return u[idx]; };
+  auto fetch = [=](int64_t idx) { return u[idx]; };
   auto make = [](double v, int64_t, bool, double) { return v; };
   auto store = [&](int64_t idx, int i, int j, int k, double q, double, double dinv) {
     const double b = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
@@ -471,7 +485,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
-  auto fetch = [=](int64_t idx, bool) { return ut[idx]; };
+  auto fetch = [=](int64_t idx) { return ut[idx]; };
   auto make = [](double v, int64_t, bool, double) { return v; };
   auto store = [=](int64_t idx, int, int, int, double q, double, double) { rho[idx] = f[idx] - q; };
   zmarch(sl, lds, fetch, make, store);
@@ -489,7 +503,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockD
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
-  auto fetch = [=](int64_t idx, bool) { return x[idx]; };
+  auto fetch = [=](int64_t idx) { return x[idx]; };
   auto make = [](T v, int64_t, bool, T) { return v; };
   auto store = [=](int64_t idx, int, int, int, T q, T, T) { y[idx] = q; };
   zmarch(sl, lds, fetch, make, store);
@@ -610,9 +624,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const T tb = T(beta);
   const bool first = t == 0;
   double a0 = 0.0;
-  auto fetch = [=](int64_t idx, bool) { return Pair<T>{r[idx], first ? T(0) : pold[idx]}; };
+  auto fetch = [=](int64_t idx) { return Pair<T>{r[idx], pold[idx]}; };
   auto make = [=](Pair<T> v, int64_t idx, bool own, T dinv) {
-    const T pn = dinv * v.a + tb * v.b;
+    const T pn = dinv * v.a + (first ? T(0) : tb * v.b);
     if (own) pnew[idx] = pn;
     return pn;
   };
@@ -762,10 +776,17 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, zb0, zb1, true);
   int epoch = 0, tfail = 0;
-  T* rb[2] = {reinterpret_cast<T*>(a.r), reinterpret_cast<T*>(a.r1)};
-  T* wb[2] = {reinterpret_cast<T*>(a.w0), reinterpret_cast<T*>(a.w1)};
-  T* sb[2] = {reinterpret_cast<T*>(a.s0), reinterpret_cast<T*>(a.s1)};
-  T* pb[2] = {reinterpret_cast<T*>(a.p0), reinterpret_cast<T*>(a.p1)};
+  // buffers chosen with selects, never through an indexed array: pointers
+  // read back from a private array lose their global address space and the
+  // loads become flat loads, which every barrier then waits for
+  T* const r0b = reinterpret_cast<T*>(a.r);
+  T* const r1b = reinterpret_cast<T*>(a.r1);
+  T* const w0b = reinterpret_cast<T*>(a.w0);
+  T* const w1b = reinterpret_cast<T*>(a.w1);
+  T* const s0b = reinterpret_cast<T*>(a.s0);
+  T* const s1b = reinterpret_cast<T*>(a.s1);
+  T* const p0b = reinterpret_cast<T*>(a.p0);
+  T* const p1b = reinterpret_cast<T*>(a.p1);
   T* __restrict__ x = reinterpret_cast<T*>(a.x);
   double rr = 0.0, bb = 0.0;
   for (int b = bfirst[s]; b < bfirst[s + 1]; ++b) {
@@ -781,9 +802,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     // u0 = D^-1 r0, w0 = A u0, gamma0 = r0'u0, delta0 = w0'u0
     double g0 = 0.0, d0 = 0.0;
     {
-      const T* __restrict__ r0 = rb[0];
-      T* __restrict__ w0 = wb[0];
-      auto fetch = [=](int64_t idx, bool) { return r0[idx]; };
+      const T* __restrict__ r0 = r0b;
+      T* __restrict__ w0 = w0b;
+      auto fetch = [=](int64_t idx) { return r0[idx]; };
       auto make = [&](T rv, int64_t, bool own, T dinv) {
         const T u = dinv * rv;
         if (own) g0 += double(rv) * double(u);
@@ -802,37 +823,40 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     double alpha = gamma / delta, beta = 0.0;
     if (!(delta > 0.0) || !isfinite(alpha) || tfail) brk = 1;
     while (!brk) {
-      const int cur = t & 1, nxt = cur ^ 1;
-      const T* __restrict__ rc = rb[cur];
-      const T* __restrict__ wc = wb[cur];
-      const T* __restrict__ sc = sb[cur];
-      const T* __restrict__ pc = pb[cur];
-      T* __restrict__ rn_ = rb[nxt];
-      T* __restrict__ wn_ = wb[nxt];
-      T* __restrict__ sn_ = sb[nxt];
-      T* __restrict__ pn_ = pb[nxt];
+      const bool odd = (t & 1) != 0;
+      const T* __restrict__ rc = odd ? r1b : r0b;
+      const T* __restrict__ wc = odd ? w1b : w0b;
+      const T* __restrict__ sc = odd ? s1b : s0b;
+      const T* __restrict__ pc = odd ? p1b : p0b;
+      T* __restrict__ rn_ = odd ? r0b : r1b;
+      T* __restrict__ wn_ = odd ? w0b : w1b;
+      T* __restrict__ sn_ = odd ? s0b : s1b;
+      T* __restrict__ pn_ = odd ? p0b : p1b;
       const bool first = t == 0;
       const T ta = T(alpha), tb = T(beta);
       double ag = 0.0, ad = 0.0, ar = 0.0;
-      auto fetch = [=](int64_t idx, bool own) {
+      auto fetch = [=](int64_t idx) {
         Five<T> v;
         v.r = rc[idx];
         v.w = wc[idx];
-        v.s = first ? T(0) : sc[idx];
-        v.p = first ? T(0) : pc[idx];
-        v.x = (first || !own) ? T(0) : x[idx];
+        v.s = sc[idx];
+        v.p = pc[idx];
+        v.x = x[idx];
         return v;
       };
       auto make = [&](const Five<T>& v, int64_t idx, bool own, T dinv) {
-        const T pn = dinv * v.r + tb * v.p;
-        const T sn = v.w + tb * v.s;
+        // the first iteration has no previous direction and no iterate (the
+        // buffers may hold anything, so select rather than scale by zero)
+        const T vp = first ? T(0) : v.p, vs = first ? T(0) : v.s, vx = first ? T(0) : v.x;
+        const T pn = dinv * v.r + tb * vp;
+        const T sn = v.w + tb * vs;
         const T rn = v.r - ta * sn;
         const T un = dinv * rn;
         if (own) {
           pn_[idx] = pn;
           sn_[idx] = sn;
           rn_[idx] = rn;
-          x[idx] = v.x + ta * pn;
+          x[idx] = vx + ta * pn;
           ag += double(rn) * double(un);
           ar += double(rn) * double(rn);
         }

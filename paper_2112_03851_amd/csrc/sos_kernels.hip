@@ -34,6 +34,15 @@
 
 namespace sos {
 
+// Element li of an array whose base is uniform across the wavefront, addressed
+// with a 32-bit byte offset: the base stays in scalar registers and each lane
+// carries one 32-bit offset shared by all arrays indexed alike.
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t li) {
+  using C = std::conditional_t<std::is_const<T>::value, const char, char>;
+  return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + li * (uint32_t)sizeof(T));
+}
+
 // ---------------------------------------------------------------------------- 1D rows
 
 template <typename T>
@@ -239,18 +248,20 @@ __device__ __forceinline__ void lds_zero(T* lds, int n) {
   for (int e = threadIdx.x; e < n; e += blockDim.x) lds[e] = T(0);
 }
 
-// The z-march, software-pipelined: fetch(idx) issues the global loads of the
-// operand at index idx (always a valid node of the subdomain) kPrefetch planes
-// ahead of its use; make(raw, idx, own, dinv) turns them into the operand
+// The z-march, software-pipelined: fetch(li) issues the global loads of the
+// operand at local index li = c + S k of the subdomain (always a valid node)
+// kPrefetch planes ahead of its use; make(raw, li, own, dinv) turns them into
+// the operand
 // (own: the plane belongs to the slot's segment; dinv: inverse diagonal).
-// store(idx, i, j, k, q, p_k, dinv) receives the finished output at plane k of
-// the slot's own segment, with the operand value p_k at that node.
+// store(li, i, j, k, q, p_k, dinv) receives the finished output at plane k of
+// the slot's own segment, with the operand value p_k at that node. Functors
+// index pointers already offset to the subdomain (uniform base + 32-bit index).
 constexpr int kPrefetch = 3;
 
 template <typename T, int CPT, bool Q, class FetchF, class MakeF, class StoreF>
 __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, FetchF& fetch, MakeF& make,
                                        StoreF& store) {
-  using Raw = decltype(fetch(int64_t(0)));
+  using Raw = decltype(fetch(uint32_t(0)));
   T acc[CPT][5];
   T pr[CPT][3];
   // prefetch ring: slot q holds the operands of the step that is congruent to
@@ -269,7 +280,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       // unconditional load from a clamped, always valid plane: a fixed number
       // of loads per step lets every use wait for its own load only
       const int kq = min(max(sl.z0[m] - 2 + q, 0), sl.nz - 1);
-      raw[m][q] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq);
+      raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq));
     }
   }
   const int steps = sl.seglen + 4;
@@ -284,14 +295,14 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] < sl.nz;
       T v = T(0);
       if (inr[m]) {
-        const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * kp[m];
+        const uint32_t li = sl.c[m] + sl.S * kp[m];
         const bool own = kp[m] >= sl.z0[m] && kp[m] < sl.z1[m];
-        v = make(raw[m][U], idx, own, slot_dinv(sl, m, kp[m]));
+        v = make(raw[m][U], li, own, slot_dinv(sl, m, kp[m]));
         lds[sl.lp[m]] = v;
       }
       pr[m][2] = v;
       const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
-      raw[m][U] = fetch(sl.off + sl.c[m] + (int64_t)sl.S * kq);
+      raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq));
     }
     __syncthreads();
 #pragma unroll
@@ -351,8 +362,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       if (sl.act[m]) {
         const int k = sl.z0[m] - 4 + step;
         if (k >= sl.z0[m] && k < sl.z1[m])
-          store(sl.off + sl.c[m] + (int64_t)sl.S * k, sl.i[m], sl.j[m], k, acc[m][0], pr[m][0],
-                slot_dinv(sl, m, k));
+          store(uint32_t(sl.c[m] + sl.S * k), sl.i[m], sl.j[m], k, acc[m][0], pr[m][0], slot_dinv(sl, m, k));
       }
       acc[m][0] = acc[m][1];
       acc[m][1] = acc[m][2];
@@ -452,12 +462,15 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int nx = sl.nx, ny = sl.ny, nz = sl.nz;
-  auto fetch = [=](int64_t idx) { return u[idx]; };
-  auto make = [](double v, int64_t, bool, double) { return v; };
-  auto store = [&](int64_t idx, int i, int j, int k, double q, double, double dinv) {
-    const double b = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
+  const double* __restrict__ ub = u + sl.off;
+  const double* __restrict__ fb = f + sl.off;
+  TO* __restrict__ rb = r + sl.off;
+  auto fetch = [=](uint32_t li) { return at(ub, li); };
+  auto make = [](double v, uint32_t, bool, double) { return v; };
+  auto store = [&](uint32_t li, int i, int j, int k, double q, double, double dinv) {
+    const double b = at(fb, li) + lam_terms(L, lam, i, j, k, nx, ny, nz);
     const TO rt = TO(b - q);
-    r[idx] = rt;
+    at(rb, li) = rt;
     const double rd = double(rt);
     a0 += rd * rd * dinv;
     a1 += rd * rd;
@@ -485,9 +498,12 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
-  auto fetch = [=](int64_t idx) { return ut[idx]; };
-  auto make = [](double v, int64_t, bool, double) { return v; };
-  auto store = [=](int64_t idx, int, int, int, double q, double, double) { rho[idx] = f[idx] - q; };
+  const double* __restrict__ utb = ut + sl.off;
+  const double* __restrict__ fb = f + sl.off;
+  double* __restrict__ rhob = rho + sl.off;
+  auto fetch = [=](uint32_t li) { return at(utb, li); };
+  auto make = [](double v, uint32_t, bool, double) { return v; };
+  auto store = [=](uint32_t li, int, int, int, double q, double, double) { at(rhob, li) = at(fb, li) - q; };
   zmarch(sl, lds, fetch, make, store);
 }
 
@@ -503,9 +519,11 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockD
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * 3 * sl.SP);
   __syncthreads();
-  auto fetch = [=](int64_t idx) { return x[idx]; };
-  auto make = [](T v, int64_t, bool, T) { return v; };
-  auto store = [=](int64_t idx, int, int, int, T q, T, T) { y[idx] = q; };
+  const T* __restrict__ xb = x + sl.off;
+  T* __restrict__ yb = y + sl.off;
+  auto fetch = [=](uint32_t li) { return at(xb, li); };
+  auto make = [](T v, uint32_t, bool, T) { return v; };
+  auto store = [=](uint32_t li, int, int, int, T q, T, T) { at(yb, li) = q; };
   zmarch(sl, lds, fetch, make, store);
 }
 
@@ -516,31 +534,34 @@ template <typename T, int CPT, bool Q>
 __device__ __forceinline__ void cg_pass_b(const Slots<T, CPT, Q>& sl, bool first, T alpha, T* __restrict__ x,
                                           const T* __restrict__ p, T* __restrict__ r, const T* __restrict__ q,
                                           double& arz, double& arr) {
+  T* __restrict__ xb = x + sl.off;
+  const T* __restrict__ pb = p + sl.off;
+  T* __restrict__ rb = r + sl.off;
+  const T* __restrict__ qb = q + sl.off;
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
     if (!sl.act[m]) continue;
-    const int64_t base = sl.off + sl.c[m];
     for (int k = sl.z0[m]; k < sl.z1[m]; k += 4) {
       T pv[4], xv[4], rv[4], qv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kk = k + u;
         if (kk < sl.z1[m]) {
-          const int64_t idx = base + (int64_t)sl.S * kk;
-          pv[u] = p[idx];
-          xv[u] = first ? T(0) : x[idx];
-          rv[u] = r[idx];
-          qv[u] = q[idx];
+          const uint32_t li = sl.c[m] + sl.S * kk;
+          pv[u] = at(pb, li);
+          xv[u] = first ? T(0) : at(xb, li);
+          rv[u] = at(rb, li);
+          qv[u] = at(qb, li);
         }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kk = k + u;
         if (kk < sl.z1[m]) {
-          const int64_t idx = base + (int64_t)sl.S * kk;
-          x[idx] = xv[u] + alpha * pv[u];
+          const uint32_t li = sl.c[m] + sl.S * kk;
+          at(xb, li) = xv[u] + alpha * pv[u];
           const T rn = rv[u] - alpha * qv[u];
-          r[idx] = rn;
+          at(rb, li) = rn;
           const double rd = double(rn);
           arz += rd * rd * double(slot_dinv(sl, m, kk));
           arr += rd * rd;
@@ -624,14 +645,18 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const T tb = T(beta);
   const bool first = t == 0;
   double a0 = 0.0;
-  auto fetch = [=](int64_t idx) { return Pair<T>{r[idx], pold[idx]}; };
-  auto make = [=](Pair<T> v, int64_t idx, bool own, T dinv) {
+  const T* __restrict__ rb = r + sl.off;
+  const T* __restrict__ pob = pold + sl.off;
+  T* __restrict__ pnb = pnew + sl.off;
+  T* __restrict__ qb = q + sl.off;
+  auto fetch = [=](uint32_t li) { return Pair<T>{at(rb, li), at(pob, li)}; };
+  auto make = [=](Pair<T> v, uint32_t li, bool own, T dinv) {
     const T pn = dinv * v.a + (first ? T(0) : tb * v.b);
-    if (own) pnew[idx] = pn;
+    if (own) at(pnb, li) = pn;
     return pn;
   };
-  auto store = [&](int64_t idx, int, int, int, T qv, T pk, T) {
-    q[idx] = qv;
+  auto store = [&](uint32_t li, int, int, int, T qv, T pk, T) {
+    at(qb, li) = qv;
     a0 += double(pk) * double(qv);
   };
   zmarch(sl, lds, fetch, make, store);
@@ -683,12 +708,14 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_add_correction(Dev d, con
   const SubDesc sd = d.subs[bd.s];
   Slots<T, CPT, false> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
+  double* __restrict__ ub = u + sl.off;
+  const T* __restrict__ xb = x + sl.off;
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
     if (!sl.act[m]) continue;
     for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
-      const int64_t idx = sl.off + sl.c[m] + (int64_t)sl.S * k;
-      u[idx] += double(x[idx]);
+      const uint32_t li = sl.c[m] + sl.S * k;
+      at(ub, li) += double(at(xb, li));
     }
   }
 }
@@ -802,16 +829,16 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     // u0 = D^-1 r0, w0 = A u0, gamma0 = r0'u0, delta0 = w0'u0
     double g0 = 0.0, d0 = 0.0;
     {
-      const T* __restrict__ r0 = r0b;
-      T* __restrict__ w0 = w0b;
-      auto fetch = [=](int64_t idx) { return r0[idx]; };
-      auto make = [&](T rv, int64_t, bool own, T dinv) {
+      const T* __restrict__ r0 = r0b + sl.off;
+      T* __restrict__ w0 = w0b + sl.off;
+      auto fetch = [=](uint32_t li) { return at(r0, li); };
+      auto make = [&](T rv, uint32_t, bool own, T dinv) {
         const T u = dinv * rv;
         if (own) g0 += double(rv) * double(u);
         return u;
       };
-      auto store = [&](int64_t idx, int, int, int, T wv, T uk, T) {
-        w0[idx] = wv;
+      auto store = [&](uint32_t li, int, int, int, T wv, T uk, T) {
+        at(w0, li) = wv;
         d0 += double(wv) * double(uk);
       };
       zmarch(sl, lds, fetch, make, store);
@@ -824,27 +851,30 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     if (!(delta > 0.0) || !isfinite(alpha) || tfail) brk = 1;
     while (!brk) {
       const bool odd = (t & 1) != 0;
-      const T* __restrict__ rc = odd ? r1b : r0b;
-      const T* __restrict__ wc = odd ? w1b : w0b;
-      const T* __restrict__ sc = odd ? s1b : s0b;
-      const T* __restrict__ pc = odd ? p1b : p0b;
-      T* __restrict__ rn_ = odd ? r0b : r1b;
-      T* __restrict__ wn_ = odd ? w0b : w1b;
-      T* __restrict__ sn_ = odd ? s0b : s1b;
-      T* __restrict__ pn_ = odd ? p0b : p1b;
+      const T* __restrict__ rc = (odd ? r1b : r0b) + sl.off;
+      const T* __restrict__ wc = (odd ? w1b : w0b) + sl.off;
+      const T* __restrict__ sc = (odd ? s1b : s0b) + sl.off;
+      const T* __restrict__ pc = (odd ? p1b : p0b) + sl.off;
+      T* __restrict__ rn_ = (odd ? r0b : r1b) + sl.off;
+      T* __restrict__ wn_ = (odd ? w0b : w1b) + sl.off;
+      T* __restrict__ sn_ = (odd ? s0b : s1b) + sl.off;
+      T* __restrict__ pn_ = (odd ? p0b : p1b) + sl.off;
+      T* __restrict__ xs = x + sl.off;
       const bool first = t == 0;
       const T ta = T(alpha), tb = T(beta);
-      double ag = 0.0, ad = 0.0, ar = 0.0;
-      auto fetch = [=](int64_t idx) {
+      // per-thread partial sums in the inner precision (a few dozen terms),
+      // combined across the block in FP64
+      T ag = T(0), ad = T(0), ar = T(0);
+      auto fetch = [=](uint32_t li) {
         Five<T> v;
-        v.r = rc[idx];
-        v.w = wc[idx];
-        v.s = sc[idx];
-        v.p = pc[idx];
-        v.x = x[idx];
+        v.r = at(rc, li);
+        v.w = at(wc, li);
+        v.s = at(sc, li);
+        v.p = at(pc, li);
+        v.x = at(xs, li);
         return v;
       };
-      auto make = [&](const Five<T>& v, int64_t idx, bool own, T dinv) {
+      auto make = [&](const Five<T>& v, uint32_t li, bool own, T dinv) {
         // the first iteration has no previous direction and no iterate (the
         // buffers may hold anything, so select rather than scale by zero)
         const T vp = first ? T(0) : v.p, vs = first ? T(0) : v.s, vx = first ? T(0) : v.x;
@@ -853,21 +883,21 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         const T rn = v.r - ta * sn;
         const T un = dinv * rn;
         if (own) {
-          pn_[idx] = pn;
-          sn_[idx] = sn;
-          rn_[idx] = rn;
-          x[idx] = vx + ta * pn;
-          ag += double(rn) * double(un);
-          ar += double(rn) * double(rn);
+          at(pn_, li) = pn;
+          at(sn_, li) = sn;
+          at(rn_, li) = rn;
+          at(xs, li) = vx + ta * pn;
+          ag += rn * un;
+          ar += rn * rn;
         }
         return un;
       };
-      auto store = [&](int64_t idx, int, int, int, T wv, T uk, T) {
-        wn_[idx] = wv;
-        ad += double(wv) * double(uk);
+      auto store = [&](uint32_t li, int, int, int, T wv, T uk, T) {
+        at(wn_, li) = wv;
+        ad += wv * uk;
       };
       zmarch(sl, lds, fetch, make, store);
-      double acc[3] = {ag, ad, ar};
+      double acc[3] = {double(ag), double(ad), double(ar)};
       block_sum(acc);
       team_sum(acc, a, s, tau, epoch++, tfail);
       ++t;
@@ -889,22 +919,23 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     }
   }
   if (t > 0) {
+    const T* __restrict__ xb = x + sl.off;
+    double* __restrict__ ub = a.u + sl.off;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (!sl.act[m]) continue;
-      const int64_t base = sl.off + sl.c[m];
       for (int k = sl.z0[m]; k < sl.z1[m]; k += 4) {
         T xv[4];
         double uv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (k + u < sl.z1[m]) {
-            xv[u] = x[base + (int64_t)sl.S * (k + u)];
-            uv[u] = a.u[base + (int64_t)sl.S * (k + u)];
+            xv[u] = at(xb, sl.c[m] + sl.S * (k + u));
+            uv[u] = at(ub, sl.c[m] + sl.S * (k + u));
           }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (k + u < sl.z1[m]) a.u[base + (int64_t)sl.S * (k + u)] = uv[u] + double(xv[u]);
+          if (k + u < sl.z1[m]) at(ub, sl.c[m] + sl.S * (k + u)) = uv[u] + double(xv[u]);
       }
     }
   }

@@ -60,7 +60,7 @@ struct sos_ctx {
   std::vector<int32_t> pairs;
   std::vector<int32_t> order;
   int64_t n_local = 0, n_lam = 0, n_nodes = 0;
-  int max_n = 0, max_face = 0;
+  int max_n = 0, max_face = 0, max_face_na = 0, max_face_nb = 0, max_shell = 0;
   Dev dev{};
   SubDesc* d_subs = nullptr;
   FaceDesc* d_faces = nullptr;
@@ -69,6 +69,7 @@ struct sos_ctx {
   Seg seg;
   // workspaces
   double *u = nullptr, *f = nullptr, *lam = nullptr, *ut = nullptr, *rho = nullptr;
+  double* fsum = nullptr;  // sum of the Robin data at every boundary-shell node
   void *r = nullptr, *x = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   void *r1 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr;  // fused CG only
   double* part = nullptr;       // 3 per segmented block
@@ -116,7 +117,7 @@ void release(sos_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
   for (auto e : c->gevents) hipEventDestroy(e);
-  void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f,
+  void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->fsum,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_cnt, c->team_part,
                   c->scal, c->ndone, c->counters};
@@ -259,6 +260,18 @@ int fused_shape(sos_ctx* c, int threads, int cpt = 0) {
   return SOS_OK;
 }
 
+// True when every block of the fused kernel (every subdomain and team member)
+// marches a single segment, so the uniform-z kernel variant applies.
+bool fused_one_segment(const sos_ctx* c) {
+  const int T = c->fused_team;
+  for (auto& s : c->subs)
+    for (int tau = 0; tau < T; ++tau) {
+      const int zlen = ((tau + 1) * s.n[2]) / T - (tau * s.n[2]) / T;
+      if (march_segments(s.n[0], s.n[1], zlen, c->fused_threads, c->fused_cpt) != 1) return false;
+    }
+  return true;
+}
+
 int set_team(sos_ctx* c, int team) {
   if (team < 1 || team > kMaxTeam) return fail(SOS_EINVAL, "team must be in [1, %d]", kMaxTeam);
   for (auto& s : c->subs)
@@ -389,18 +402,20 @@ FusedArgs fused_args(sos_ctx* c) {
   a.team = c->fused_team;
   a.team_cnt = c->team_cnt;
   a.team_part = c->team_part;
+  a.zu = fused_one_segment(c) ? 1 : 0;
   return a;
 }
 
 // One outer iteration in the batched form; ev (optional) brackets the fused kernel.
 int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
-  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part,
+  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->lam, c->fsum, st));
+  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->fsum, c->r, c->part,
                          c->fused_team > 1 ? c->team_cnt : nullptr, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
-  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face, c->u, c->lam, st));
+  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
   return SOS_OK;
 }
 
@@ -408,7 +423,8 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
 int stepwise_iteration(sos_ctx* c) {
   hipStream_t st = c->stream;
   const SegLaunch& L = c->seg.L;
-  HIPCHK(launch_residual(c->dev, L, c->fp32, c->u, c->f, c->lam, c->r, c->part, nullptr, st));
+  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->lam, c->fsum, st));
+  HIPCHK(launch_residual(c->dev, L, c->fp32, c->u, c->f, c->fsum, c->r, c->part, nullptr, st));
   HIPCHK(launch_cg_init(c->dev, L, c->part, c->opts.inner_tol, c->opts.inner_abs, c->scal, c->ndone, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.timing) {
@@ -444,7 +460,7 @@ int stepwise_iteration(sos_ctx* c) {
     hipEventDestroy(e1);
   }
   HIPCHK(launch_add_correction(c->dev, L, c->fp32, c->u, c->x, c->scal, st));
-  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face, c->u, c->lam, st));
+  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
   return SOS_OK;
 }
 
@@ -613,7 +629,8 @@ int autotune(sos_ctx* c) {
       bool ok = true;
       for (int rep = 0; rep < 2 && ok; ++rep) {
         HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
-        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->lam, c->r, c->part,
+        HIPCHK(launch_face_sum(c->dev, c->max_shell, c->lam, c->fsum, st));
+        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->fsum, c->r, c->part,
                                team > 1 ? c->team_cnt : nullptr, st));
         HIPCHK(hipEventRecord(e0, st));
         if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
@@ -773,6 +790,12 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
         d.off = off;
         off = align64(off + n);
         c->max_n = std::max<int>(c->max_n, (int)n);
+        {  // boundary-shell nodes, counted as the face-sum kernel enumerates them
+          const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+          const int ix = std::max(nx - 2, 0), iy = std::max(ny - 2, 0);
+          const int shell = (nx > 1 ? 2 : 1) * ny * nz + (ny > 1 ? 2 : 1) * ix * nz + (nz > 1 ? 2 : 1) * ix * iy;
+          c->max_shell = std::max(c->max_shell, shell);
+        }
       }
   c->n_local = off;
   // directed faces: by s, axis, side
@@ -796,6 +819,8 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
         F.opp = -1;
         loff += (int64_t)F.na * F.nb;
         c->max_face = std::max(c->max_face, F.na * F.nb);
+        c->max_face_na = std::max(c->max_face_na, F.na);
+        c->max_face_nb = std::max(c->max_face_nb, F.nb);
         d.face[2 * a + side] = (int32_t)c->faces.size();
         c->faces.push_back(F);
       }
@@ -819,6 +844,14 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
     return fail(SOS_ESTATE, "no usable HIP device");
   }
   c->lds_limit = prop.sharedMemPerBlock;
+  {
+    const size_t ex_lds = 2 * sizeof(double) * (size_t)(c->max_face_na + 4) * (size_t)(kExchangeRows + 4);
+    if (ex_lds > c->lds_limit) {
+      release(c);
+      return fail(SOS_EINVAL, "interface face of %d nodes along its first axis needs %zu bytes of LDS (limit %zu)",
+                  c->max_face_na, ex_lds, (size_t)prop.sharedMemPerBlock);
+    }
+  }
   c->tuned = opts->block != 0 && opts->team != 0;
   if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block)) || (rc = set_team(c, opts->team ? opts->team : 1))) {
     release(c);
@@ -839,6 +872,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
       (rc = dalloc(&c->d_pairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||
       (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
       (rc = dalloc(&c->u, c->n_local)) || (rc = dalloc(&c->f, c->n_local)) || (rc = dalloc(&c->lam, c->n_lam)) ||
+      (rc = dalloc(&c->fsum, c->n_local)) ||
       (rc = dalloc(&c->ut, c->n_local)) || (rc = dalloc(&c->rho, c->n_local)) ||
       (rc = dalloc_v(&c->r, c->n_local * es)) || (rc = dalloc_v(&c->x, c->n_local * es)) ||
       (rc = dalloc_v(&c->p0, c->n_local * es)) || (rc = dalloc_v(&c->p1, c->n_local * es)) ||
@@ -886,6 +920,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
   if (e == hipSuccess)
     e = hipMemcpy(c->seg.d_bfirst, c->seg.bfirst.data(), c->seg.bfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->f, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->fsum, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->u, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->lam, 0, std::max<int64_t>(1, c->n_lam) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->ut, 0, c->n_local * sizeof(double));

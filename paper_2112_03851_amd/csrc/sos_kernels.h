@@ -40,11 +40,14 @@ __host__ __device__ inline int march_segments(int nx, int ny, int zlen, int thre
   if (g > gz) g = gz;
   return g < 1 ? 1 : g;
 }
-// LDS bytes of such a march: three zero-padded planes per segment.
+// LDS planes per march segment: the operand (two, alternating by step) and the
+// two y-pass results, each zero-padded by kPad.
+constexpr int kPlanes = 4;
+// LDS bytes of such a march.
 __host__ __device__ inline size_t march_lds_bytes(int nx, int ny, int zlen, int threads, int cpt,
                                                   size_t elem) {
   size_t sp = (size_t)(nx + 2 * kPad) * (size_t)(ny + 2 * kPad);
-  return 3 * sp * (size_t)march_segments(nx, ny, zlen, threads, cpt) * elem;
+  return kPlanes * sp * (size_t)march_segments(nx, ny, zlen, threads, cpt) * elem;
 }
 
 // f_s from a per-element density (FP64), for all subdomains.
@@ -53,9 +56,12 @@ hipError_t launch_load_density(const Dev& d, int max_n, const double* drho, doub
 // f_s = f_nodes / multiplicity.
 hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, double* f_loc,
                              hipStream_t st);
-// r = f + sum R^T lambda - A u (FP64 apply), stored as Tr; partials rz, rr, bb per block.
+// g = sum_j R_sj^T lambda_{s<-j} at the boundary shell nodes of every subdomain.
+hipError_t launch_face_sum(const Dev& d, int max_shell, const double* lam, double* g, hipStream_t st);
+// r = f + g - A u (FP64 apply, g from launch_face_sum), stored as Tr; partials
+// rz, rr, bb per block.
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u,
-                           const double* f, const double* lam, void* r_out, double* part,
+                           const double* f, const double* g, void* r_out, double* part,
                            unsigned* team_cnt, hipStream_t st);
 // Per-subdomain CG scalars from the residual partials (stepwise path).
 hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel,
@@ -85,12 +91,14 @@ struct FusedArgs {
   int32_t team;                     // blocks per subdomain (1: no inter-block sync)
   unsigned* team_cnt;               // n_sub barrier counters (zeroed by the residual kernel)
   double* team_part;                // n_sub * team * 2 * 4 partial sums
+  int32_t zu;                       // every block marches one segment (uniform z variant)
 };
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st);
 // Robin exchange over all interfaces (in place, both directions).
-hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_face,
-                           const double* u, double* lam, hipStream_t st);
+constexpr int kExchangeRows = 16;  // face rows per block of the exchange kernel
+hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_na,
+                           int32_t max_nb, const double* u, double* lam, hipStream_t st);
 // Glue: utilde = average of copies (local layout).
 hipError_t launch_glue(const Dev& d, int max_n, const double* u, double* ut, hipStream_t st);
 // rho = f - K^N utilde (FP64, Neumann local stiffness).

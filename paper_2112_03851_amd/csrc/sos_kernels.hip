@@ -43,6 +43,7 @@ __device__ __forceinline__ T& at(T* base, uint32_t li) {
   return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + li * (uint32_t)sizeof(T));
 }
 
+
 // ---------------------------------------------------------------------------- 1D rows
 
 template <typename T>
@@ -116,6 +117,7 @@ struct Slots {
   int nx, ny, nz, S, PX, SP, G, seglen;
   int64_t off;
   int c[CPT], i[CPT], j[CPT], g[CPT], z0[CPT], z1[CPT], lp[CPT];
+  int uz0, uz1;  // the block's z-range (the segment of every slot when G == 1)
   bool act[CPT];
   T kx0[CPT], mx0[CPT], kx2[CPT], mx2[CPT];
   T ky0[CPT], my0[CPT], ky2[CPT], my2[CPT];
@@ -140,6 +142,8 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& 
   const int NT = blockDim.x;
   const int zlen = zb1 - zb0;
   sl.G = march_segments(sl.nx, sl.ny, zlen, NT, CPT);
+  sl.uz0 = zb0;
+  sl.uz1 = zb1;
   sl.seglen = (zlen + sl.G - 1) / sl.G;
   const T ksx = T(geo.ks[0]), msx = T(geo.ms[0]);
   const T ksy = T(geo.ks[1]), msy = T(geo.ms[1]);
@@ -187,7 +191,7 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& 
     const int i = col % sl.nx, j = col / sl.nx;
     sl.i[m] = i;
     sl.j[m] = j;
-    sl.lp[m] = g * 3 * sl.SP + (i + kPad) + sl.PX * (j + kPad);
+    sl.lp[m] = g * kPlanes * sl.SP + (i + kPad) + sl.PX * (j + kPad);
     Row<T> rx = row_of<T>(i + d.klo[0], d.ne2[0], ksx, msx, robin ? T(d.elo[0]) : T(0),
                           robin ? T(d.ehi[0]) : T(0));
     Row<T> ry = row_of<T>(j + d.klo[1], d.ne2[1], ksy, msy, robin ? T(d.elo[1]) : T(0),
@@ -253,14 +257,42 @@ __device__ __forceinline__ void lds_zero(T* lds, int n) {
 // kPrefetch planes ahead of its use; make(raw, li, own, dinv) turns them into
 // the operand
 // (own: the plane belongs to the slot's segment; dinv: inverse diagonal).
-// store(li, i, j, k, q, p_k, dinv) receives the finished output at plane k of
-// the slot's own segment, with the operand value p_k at that node. Functors
-// index pointers already offset to the subdomain (uniform base + 32-bit index).
+// store(li, en, i, j, k, q, p_k, dinv) receives the finished output at plane k
+// of the slot's own segment, with the operand value p_k at that node (or the
+// value make() carried for it), when en; make() and store() are called on every
+// step and write nothing when own / en is false. Functors index pointers
+// already offset to the subdomain (uniform base + 32-bit index).
 constexpr int kPrefetch = 3;
 
-template <typename T, int CPT, bool Q, class FetchF, class MakeF, class StoreF>
+// make() returns the operand of the stencil, or an operand with a separate
+// value carried to store() (default: the operand itself).
+template <typename T>
+struct OpCarry {
+  T op, carry;
+};
+template <typename T>
+__device__ __forceinline__ T op_of(T v) { return v; }
+template <typename T>
+__device__ __forceinline__ T op_of(const OpCarry<T>& v) { return v.op; }
+template <typename T>
+__device__ __forceinline__ T carry_of(T v) { return v; }
+template <typename T>
+__device__ __forceinline__ T carry_of(const OpCarry<T>& v) { return v.carry; }
+
+// ZU: the block marches one segment (G == 1), so every plane index is uniform
+// across the block and the z-dependent row coefficients, the diagonal's
+// z-kind and the plane tests run on the scalar unit.
+template <bool ZU = false, typename T, int CPT, bool Q, class FetchF, class MakeF, class StoreF>
 __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, FetchF& fetch, MakeF& make,
                                        StoreF& store) {
+  auto zlo = [&](int m) {
+    if constexpr (ZU) return sl.uz0;
+    else return sl.z0[m];
+  };
+  auto zhi = [&](int m) {
+    if constexpr (ZU) return sl.uz1;
+    else return sl.z1[m];
+  };
   using Raw = decltype(fetch(uint32_t(0)));
   T acc[CPT][5];
   T pr[CPT][3];
@@ -279,7 +311,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     for (int q = 0; q < kPrefetch; ++q) {
       // unconditional load from a clamped, always valid plane: a fixed number
       // of loads per step lets every use wait for its own load only
-      const int kq = min(max(sl.z0[m] - 2 + q, 0), sl.nz - 1);
+      const int kq = min(max(zlo(m) - 2 + q, 0), sl.nz - 1);
       raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq));
     }
   }
@@ -287,20 +319,23 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
   const int PX = sl.PX, SP = sl.SP;
   auto one_step = [&](auto ucst, int step) {
     constexpr int U = decltype(ucst)::value;
+    // the operand plane alternates between two LDS planes: the next step's
+    // writes never meet this step's x-pass reads of it (second-order terms)
+    const int po = (step & 1) ? 3 * SP : 0;
     bool inr[CPT];
     int kp[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-      kp[m] = sl.z0[m] - 2 + step;
+      kp[m] = zlo(m) - 2 + step;
       inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] < sl.nz;
-      T v = T(0);
-      if (inr[m]) {
-        const uint32_t li = sl.c[m] + sl.S * kp[m];
-        const bool own = kp[m] >= sl.z0[m] && kp[m] < sl.z1[m];
-        v = make(raw[m][U], li, own, slot_dinv(sl, m, kp[m]));
-        lds[sl.lp[m]] = v;
-      }
-      pr[m][2] = v;
+      // make() runs on every step (on a clamped, valid plane outside the
+      // subdomain, with own = false): its stores are off, its result unused
+      const int kc = min(max(kp[m], 0), sl.nz - 1);
+      const bool own = sl.act[m] && kp[m] >= zlo(m) && kp[m] < zhi(m);
+      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, slot_dinv(sl, m, kc));
+      const T v = inr[m] ? T(op_of(mv)) : T(0);
+      if (inr[m]) lds[sl.lp[m] + po] = v;
+      pr[m][2] = inr[m] ? T(carry_of(mv)) : T(0);
       const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
       raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq));
     }
@@ -308,7 +343,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (inr[m]) {
-        const T* P = lds + sl.lp[m];
+        const T* P = lds + sl.lp[m] + po;
         const T a0 = P[0];
         const T s1 = P[-PX] + P[PX];
         const T s2 = P[-2 * PX] + P[2 * PX];
@@ -333,7 +368,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
           // second-order faces q (tangential stiffness with plain 1D factors):
           // an x-face adds q (Ky (x) Mz + My (x) Kz) on its plane, a y-face
           // q (Kx (x) Mz + Mx (x) Kz), a z-face q (Kx (x) My + Mx (x) Ky)
-          const T* P = lds + sl.lp[m];
+          const T* P = lds + sl.lp[m] + po;
           const T p0 = P[0], p1 = P[-1] + P[1], p2 = P[-2] + P[2];
           const T pm = sl.mx0[m] * p0 + sl.mx1 * p1 + sl.mx2[m] * p2;
           const T pk = (sl.kx0[m] - sl.ex[m]) * p0 + sl.kx1 * p1 + sl.kx2[m] * p2;
@@ -359,10 +394,11 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     }
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-      if (sl.act[m]) {
-        const int k = sl.z0[m] - 4 + step;
-        if (k >= sl.z0[m] && k < sl.z1[m])
-          store(uint32_t(sl.c[m] + sl.S * k), sl.i[m], sl.j[m], k, acc[m][0], pr[m][0], slot_dinv(sl, m, k));
+      {
+        const int k = zlo(m) - 4 + step;
+        const bool en = sl.act[m] && k >= zlo(m) && k < zhi(m);
+        const int kc = min(max(k, 0), sl.nz - 1);
+        store(uint32_t(sl.c[m] + sl.S * kc), en, sl.i[m], sl.j[m], kc, acc[m][0], pr[m][0], slot_dinv(sl, m, kc));
       }
       acc[m][0] = acc[m][1];
       acc[m][1] = acc[m][2];
@@ -443,9 +479,48 @@ __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int
 // ---------------------------------------------------------------------------- outer kernels
 
 // r = f + sum_F R^T lambda_F - A u, rounded to TO; partials (r'D^-1 r, r'r, b'b).
+// g = sum_j R_sj^T lambda_{s<-j} on the boundary shell of every subdomain
+// (each shell node written once; nodes off the shell are never written and
+// stay zero).
+__global__ void k_face_sum(Dev d, const double* __restrict__ lam, double* __restrict__ g) {
+  const SubDesc sd = d.subs[blockIdx.y];
+  const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2];
+  const int xs = nx > 1 ? 2 : 1, ys = ny > 1 ? 2 : 1, zs = nz > 1 ? 2 : 1;
+  const int ix = max(nx - 2, 0), iy = max(ny - 2, 0);
+  const int n_x = xs * ny * nz, n_y = ys * ix * nz, n_z = zs * ix * iy;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < n_x) {  // x planes: all (j, k)
+    const int side = t / (ny * nz), e = t % (ny * nz);
+    i = side ? nx - 1 : 0;
+    j = e % ny;
+    k = e / ny;
+  } else if ((t -= n_x) < n_y) {  // y planes: interior i, all k
+    const int side = t / (ix * nz), e = t % (ix * nz);
+    j = side ? ny - 1 : 0;
+    i = 1 + e % ix;
+    k = e / ix;
+  } else if ((t -= n_y) < n_z) {  // z planes: interior i and j
+    const int side = t / (ix * iy), e = t % (ix * iy);
+    k = side ? nz - 1 : 0;
+    i = 1 + e % ix;
+    j = 1 + e / ix;
+  } else {
+    return;
+  }
+  const LamOff L = lam_offsets(d, sd);
+  g[sd.off + i + (int64_t)nx * (j + (int64_t)ny * k)] = lam_terms(L, lam, i, j, k, nx, ny, nz);
+}
+
+template <typename T>
+struct Three {
+  T a, b, c;
+};
+
+// r = f + g - A u with g = sum_j R_sj^T lambda_{s<-j} (the face sums).
 template <typename TO, int CPT, bool Q>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
-                                                   const double* __restrict__ f, const double* __restrict__ lam,
+                                                   const double* __restrict__ f, const double* __restrict__ g,
                                                    TO* __restrict__ r, double* __restrict__ part,
                                                    unsigned* __restrict__ team_cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -457,18 +532,17 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   const SubDesc sd = d.subs[bd.s];
   Slots<double, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  const LamOff L = lam_offsets(d, sd);
-  lds_zero(lds, sl.G * 3 * sl.SP);
+  lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  const int nx = sl.nx, ny = sl.ny, nz = sl.nz;
   const double* __restrict__ ub = u + sl.off;
   const double* __restrict__ fb = f + sl.off;
+  const double* __restrict__ gb = g + sl.off;
   TO* __restrict__ rb = r + sl.off;
-  auto fetch = [=](uint32_t li) { return at(ub, li); };
-  auto make = [](double v, uint32_t, bool, double) { return v; };
-  auto store = [&](uint32_t li, int i, int j, int k, double q, double, double dinv) {
-    const double b = at(fb, li) + lam_terms(L, lam, i, j, k, nx, ny, nz);
+  auto fetch = [=](uint32_t li) { return Three<double>{at(ub, li), at(fb, li), at(gb, li)}; };
+  auto make = [](const Three<double>& v, uint32_t, bool, double) { return OpCarry<double>{v.a, v.b + v.c}; };
+  auto store = [&](uint32_t li, bool en, int, int, int, double q, double b, double dinv) {
+    if (!en) return;
     const TO rt = TO(b - q);
     at(rb, li) = rt;
     const double rd = double(rt);
@@ -496,14 +570,16 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
   const SubDesc sd = d.subs[bd.s];
   Slots<double, CPT, false> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
-  lds_zero(lds, sl.G * 3 * sl.SP);
+  lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   const double* __restrict__ utb = ut + sl.off;
   const double* __restrict__ fb = f + sl.off;
   double* __restrict__ rhob = rho + sl.off;
   auto fetch = [=](uint32_t li) { return at(utb, li); };
   auto make = [](double v, uint32_t, bool, double) { return v; };
-  auto store = [=](uint32_t li, int, int, int, double q, double, double) { at(rhob, li) = at(fb, li) - q; };
+  auto store = [=](uint32_t li, bool en, int, int, int, double q, double, double) {
+    if (en) at(rhob, li) = at(fb, li) - q;
+  };
   zmarch(sl, lds, fetch, make, store);
 }
 
@@ -517,13 +593,15 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockD
   const SubDesc sd = d.subs[bd.s];
   Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  lds_zero(lds, sl.G * 3 * sl.SP);
+  lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   const T* __restrict__ xb = x + sl.off;
   T* __restrict__ yb = y + sl.off;
   auto fetch = [=](uint32_t li) { return at(xb, li); };
   auto make = [](T v, uint32_t, bool, T) { return v; };
-  auto store = [=](uint32_t li, int, int, int, T q, T, T) { at(yb, li) = q; };
+  auto store = [=](uint32_t li, bool en, int, int, int, T q, T, T) {
+    if (en) at(yb, li) = q;
+  };
   zmarch(sl, lds, fetch, make, store);
 }
 
@@ -640,7 +718,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const SubDesc sd = d.subs[s];
   Slots<T, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  lds_zero(lds, sl.G * 3 * sl.SP);
+  lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   const T tb = T(beta);
   const bool first = t == 0;
@@ -655,7 +733,8 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
     if (own) at(pnb, li) = pn;
     return pn;
   };
-  auto store = [&](uint32_t li, int, int, int, T qv, T pk, T) {
+  auto store = [&](uint32_t li, bool en, int, int, int, T qv, T pk, T) {
+    if (!en) return;
     at(qb, li) = qv;
     a0 += double(pk) * double(qv);
   };
@@ -781,7 +860,7 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 // gamma = r'u, delta = w'u and r'r; then beta = gamma/gamma_old and
 // alpha = gamma / (delta - beta gamma / alpha_old). r, w, s, p are double
 // buffered (halo planes of one segment are read while another writes).
-template <typename T, int CPT, bool Q>
+template <typename T, int CPT, bool Q, bool ZU>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
@@ -821,10 +900,11 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     bb += a.res_part[3 * b + 2];
   }
   const double stop2 = fmax(a.tol_rel * a.tol_rel * rr, a.tol_abs * a.tol_abs * bb);
-  lds_zero(lds, sl.G * 3 * sl.SP);
+  lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   int t = 0, brk = 0;
   if (!isfinite(rr)) brk = 1;
+  if (ZU && sl.G != 1) brk = 1;  // the host selects ZU only when every block has one segment
   if (!brk && rr > stop2 && a.max_inner > 0) {
     // u0 = D^-1 r0, w0 = A u0, gamma0 = r0'u0, delta0 = w0'u0
     double g0 = 0.0, d0 = 0.0;
@@ -837,11 +917,12 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         if (own) g0 += double(rv) * double(u);
         return u;
       };
-      auto store = [&](uint32_t li, int, int, int, T wv, T uk, T) {
+      auto store = [&](uint32_t li, bool en, int, int, int, T wv, T uk, T) {
+        if (!en) return;
         at(w0, li) = wv;
         d0 += double(wv) * double(uk);
       };
-      zmarch(sl, lds, fetch, make, store);
+      zmarch<ZU>(sl, lds, fetch, make, store);
     }
     double acc0[2] = {g0, d0};
     block_sum(acc0);
@@ -855,11 +936,11 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       const T* __restrict__ wc = (odd ? w1b : w0b) + sl.off;
       const T* __restrict__ sc = (odd ? s1b : s0b) + sl.off;
       const T* __restrict__ pc = (odd ? p1b : p0b) + sl.off;
+      T* __restrict__ xs = x + sl.off;
       T* __restrict__ rn_ = (odd ? r0b : r1b) + sl.off;
       T* __restrict__ wn_ = (odd ? w0b : w1b) + sl.off;
       T* __restrict__ sn_ = (odd ? s0b : s1b) + sl.off;
       T* __restrict__ pn_ = (odd ? p0b : p1b) + sl.off;
-      T* __restrict__ xs = x + sl.off;
       const bool first = t == 0;
       const T ta = T(alpha), tb = T(beta);
       // per-thread partial sums in the inner precision (a few dozen terms),
@@ -892,11 +973,12 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         }
         return un;
       };
-      auto store = [&](uint32_t li, int, int, int, T wv, T uk, T) {
+      auto store = [&](uint32_t li, bool en, int, int, int, T wv, T uk, T) {
+        if (!en) return;
         at(wn_, li) = wv;
         ad += wv * uk;
       };
-      zmarch(sl, lds, fetch, make, store);
+      zmarch<ZU>(sl, lds, fetch, make, store);
       double acc[3] = {double(ag), double(ad), double(ar)};
       block_sum(acc);
       team_sum(acc, a, s, tau, epoch++, tfail);
@@ -950,73 +1032,100 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
 
 // ---------------------------------------------------------------------------- exchange
 
-// (cp M_F + cq K_F) w at face node (a, b) of the face F of subdomain F.s:
-// tangential 1D mass and plain stiffness rows (K_F = Ka (x) Mb + Ma (x) Kb).
-__device__ __forceinline__ double face_op_apply(const Dev& d, const FaceDesc& F, const double* u, int a, int b,
-                                                double cp, double cq) {
+// Position of face F's nodes in the concatenated local vectors: node (a, b)
+// of the face (first tangential axis fastest) is at base + a sa + b sb.
+struct FaceGeo {
+  int64_t base, sa, sb;
+  int kla, klb, nea, neb;
+  double msa, msb, ksa, ksb;
+};
+
+__device__ __forceinline__ FaceGeo face_geo(const Dev& d, const FaceDesc& F) {
   const SubDesc& sd = d.subs[F.s];
   const int ax = F.axis;
   // tangential axes: x-face (y, z), y-face (x, z), z-face (x, y)
-  const int na = ax == 0 ? sd.n[1] : sd.n[0];
-  const int nb = ax == 2 ? sd.n[1] : sd.n[2];
-  const int kla = ax == 0 ? sd.klo[1] : sd.klo[0];
-  const int klb = ax == 2 ? sd.klo[1] : sd.klo[2];
-  const int nea = ax == 0 ? sd.ne2[1] : sd.ne2[0];
-  const int neb = ax == 2 ? sd.ne2[1] : sd.ne2[2];
-  const double msa = ax == 0 ? d.geo.ms[1] : d.geo.ms[0];
-  const double msb = ax == 2 ? d.geo.ms[1] : d.geo.ms[2];
-  const double ksa = ax == 0 ? d.geo.ks[1] : d.geo.ks[0];
-  const double ksb = ax == 2 ? d.geo.ks[1] : d.geo.ks[2];
-  const int ta = ax == 0 ? 1 : 0;
-  const int tb = ax == 2 ? 1 : 2;
-  const int nax = ax == 0 ? sd.n[0] : (ax == 1 ? sd.n[1] : sd.n[2]);
-  const int plane = F.side ? nax - 1 : 0;
-  const Row<double> ra = row_of<double>(a + kla, nea, ksa, msa, 0.0, 0.0);
-  const Row<double> rb = row_of<double>(b + klb, neb, ksb, msb, 0.0, 0.0);
-  const int sx = 1, sy = sd.n[0], sz = sd.n[0] * sd.n[1];
-  const int64_t sa = ta == 0 ? sx : sy;
-  const int64_t sb = tb == 1 ? sy : sz;
-  const int64_t sn = ax == 0 ? sx : (ax == 1 ? sy : sz);
-  const int64_t base = sd.off + (int64_t)plane * sn;
-  double acc = 0.0;
-#pragma unroll
-  for (int ob = 0; ob < 5; ++ob) {
-    const int bb = b + ob - 2;
-    const double mb = (ob == 2) ? rb.m0 : ((ob == 1 || ob == 3) ? 2.0 * msb : rb.m2);
-    const double kb = (ob == 2) ? rb.k0 : ((ob == 1 || ob == 3) ? -8.0 * ksb : rb.k2);
-    if (bb < 0 || bb >= nb) continue;
-    double rm = 0.0, rk = 0.0;
-#pragma unroll
-    for (int oa = 0; oa < 5; ++oa) {
-      const int aa = a + oa - 2;
-      const double ma = (oa == 2) ? ra.m0 : ((oa == 1 || oa == 3) ? 2.0 * msa : ra.m2);
-      const double ka = (oa == 2) ? ra.k0 : ((oa == 1 || oa == 3) ? -8.0 * ksa : ra.k2);
-      if (aa < 0 || aa >= na) continue;
-      const double w = u[base + (int64_t)aa * sa + (int64_t)bb * sb];
-      rm += ma * w;
-      rk += ka * w;
-    }
-    acc += cp * mb * rm + cq * (kb * rm + mb * rk);
-  }
-  return acc;
+  const int ta = ax == 0 ? 1 : 0, tb = ax == 2 ? 1 : 2;
+  FaceGeo g;
+  g.kla = sd.klo[ta];
+  g.klb = sd.klo[tb];
+  g.nea = sd.ne2[ta];
+  g.neb = sd.ne2[tb];
+  g.msa = d.geo.ms[ta];
+  g.msb = d.geo.ms[tb];
+  g.ksa = d.geo.ks[ta];
+  g.ksb = d.geo.ks[tb];
+  const int64_t st[3] = {1, sd.n[0], (int64_t)sd.n[0] * sd.n[1]};
+  g.sa = st[ta];
+  g.sb = st[tb];
+  const int plane = F.side ? sd.n[ax] - 1 : 0;
+  g.base = sd.off + (int64_t)plane * st[ax];
+  return g;
 }
 
-// lambda_{s<-j} <- -lambda_{j<-s} + (A_sj + A_js) u_j,
-// lambda_{j<-s} <- -lambda_{s<-j} + (A_sj + A_js) u_s,   A = p M_F + q K_F.
-__global__ void k_exchange(Dev d, const int32_t* __restrict__ pair_faces, const double* __restrict__ u,
-                           double* __restrict__ lam) {
+// One block per (interface pair, band of kExchangeRows face rows): both sides' face
+// values are gathered once into zero-padded LDS tiles (two halo rows and
+// columns: the tangential 1D rows reach +-2), then
+//   lambda_{s<-j} <- -lambda_{j<-s} + (A_sj + A_js) u_j,
+//   lambda_{j<-s} <- -lambda_{s<-j} + (A_sj + A_js) u_s,   A = p M_F + q K_F,
+// with M_F = Ma (x) Mb and K_F = Ka (x) Mb + Ma (x) Kb (plain 1D factors).
+constexpr int kExThreads = 256;
+
+__global__ void __launch_bounds__(kExThreads) k_exchange(Dev d, const int32_t* __restrict__ pair_faces,
+                                                         const double* __restrict__ u, double* __restrict__ lam) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Us = reinterpret_cast<double*>(smem);
   const FaceDesc F = d.faces[pair_faces[blockIdx.y]];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= F.na * F.nb) return;
-  const FaceDesc Gf = d.faces[F.opp];
-  const int a = t % F.na, b = t / F.na;
-  const double cp = F.p + Gf.p, cq = F.q + Gf.q;
-  const double aus = face_op_apply(d, F, u, a, b, cp, cq);
-  const double auj = face_op_apply(d, Gf, u, a, b, cp, cq);
-  const double lf = lam[F.lam_off + t];
-  const double lg = lam[Gf.lam_off + t];
-  lam[F.lam_off + t] = -lg + auj;
-  lam[Gf.lam_off + t] = -lf + aus;
+  const int na = F.na, nb = F.nb;
+  const int b0 = blockIdx.x * kExchangeRows;
+  if (b0 >= nb) return;
+  const FaceDesc G = d.faces[F.opp];
+  const int rows = min(kExchangeRows, nb - b0);
+  const int W = na + 4, H = rows + 4;
+  double* Uj = Us + W * H;
+  const FaceGeo gs = face_geo(d, F), gj = face_geo(d, G);
+  for (int e = threadIdx.x; e < W * H; e += blockDim.x) {
+    const int a = e % W - 2, b = e / W + b0 - 2;
+    double vs = 0.0, vj = 0.0;
+    if (a >= 0 && a < na && b >= 0 && b < nb) {
+      vs = u[gs.base + a * gs.sa + b * gs.sb];
+      vj = u[gj.base + a * gj.sa + b * gj.sb];
+    }
+    Us[e] = vs;
+    Uj[e] = vj;
+  }
+  __syncthreads();
+  const double cp = F.p + G.p, cq = F.q + G.q;
+  for (int t = threadIdx.x; t < na * rows; t += blockDim.x) {
+    const int a = t % na, b = b0 + t / na;
+    // both subdomains share the tangential grid of the face
+    const Row<double> ra = row_of<double>(a + gs.kla, gs.nea, gs.ksa, gs.msa, 0.0, 0.0);
+    const Row<double> rb = row_of<double>(b + gs.klb, gs.neb, gs.ksb, gs.msb, 0.0, 0.0);
+    const double ma[5] = {ra.m2, 2.0 * gs.msa, ra.m0, 2.0 * gs.msa, ra.m2};
+    const double ka[5] = {ra.k2, -8.0 * gs.ksa, ra.k0, -8.0 * gs.ksa, ra.k2};
+    const double mb[5] = {rb.m2, 2.0 * gs.msb, rb.m0, 2.0 * gs.msb, rb.m2};
+    const double kb[5] = {rb.k2, -8.0 * gs.ksb, rb.k0, -8.0 * gs.ksb, rb.k2};
+    double as = 0.0, aj = 0.0;
+#pragma unroll
+    for (int ob = 0; ob < 5; ++ob) {
+      const double* rs = Us + (b - b0 + ob) * W + a;
+      const double* rj = Uj + (b - b0 + ob) * W + a;
+      double ms_ = 0.0, ks_ = 0.0, mj = 0.0, kj = 0.0;
+#pragma unroll
+      for (int oa = 0; oa < 5; ++oa) {
+        ms_ += ma[oa] * rs[oa];
+        ks_ += ka[oa] * rs[oa];
+        mj += ma[oa] * rj[oa];
+        kj += ka[oa] * rj[oa];
+      }
+      as += cp * mb[ob] * ms_ + cq * (kb[ob] * ms_ + mb[ob] * ks_);
+      aj += cp * mb[ob] * mj + cq * (kb[ob] * mj + mb[ob] * kj);
+    }
+    const int64_t t2 = a + (int64_t)na * b;
+    const double lf = lam[F.lam_off + t2];
+    const double lg = lam[G.lam_off + t2];
+    lam[F.lam_off + t2] = -lg + aj;
+    lam[G.lam_off + t2] = -lf + as;
+  }
 }
 
 // ---------------------------------------------------------------------------- glue and residual
@@ -1258,6 +1367,12 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
   return hipGetLastError();
 }
 
+hipError_t launch_face_sum(const Dev& d, int max_shell, const double* lam, double* g, hipStream_t st) {
+  if (max_shell <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_sum, dim3((max_shell + 255) / 256, d.geo.n_sub), dim3(256), 0, st, d, lam, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u, const double* f,
                            const double* lam, void* r_out, double* part, unsigned* team_cnt, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
@@ -1327,12 +1442,12 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
   return hipGetLastError();
 }
 
-template <typename T, int C, bool Q>
+template <typename T, int C, bool Q, bool ZU>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
                                    hipStream_t st) {
   const dim3 grid(d.geo.n_sub * a.team), block(threads);
   if (a.team <= 1) {
-    hipLaunchKernelGGL((k_fused_cg<T, C, Q>), grid, block, lds, st, d, L.bfirst, a);
+    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU>), grid, block, lds, st, d, L.bfirst, a);
     return hipGetLastError();
   }
   // team barriers spin: every block of the grid must be resident at once
@@ -1340,25 +1455,31 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
   const int32_t* bf = L.bfirst;
   FusedArgs aa = a;
   void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q>, grid, block, args, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q, ZU>, grid, block, args, (unsigned)lds, st);
 }
 
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
-    if (fp32) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q>(d, L, threads, lds, a, st)));
+    if (fp32 && a.zu) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true>(d, L, threads, lds, a, st)));
+    } else if (fp32) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, false>(d, L, threads, lds, a, st)));
+    } else if (a.zu) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, true>(d, L, threads, lds, a, st)));
     } else {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q>(d, L, threads, lds, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, false>(d, L, threads, lds, a, st)));
     }
   });
   return hipSuccess;
 }
 
-hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_face,
-                           const double* u, double* lam, hipStream_t st) {
+hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_na,
+                           int32_t max_nb, const double* u, double* lam, hipStream_t st) {
   if (n_pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_exchange, dim3((max_face + 255) / 256, n_pairs), dim3(256), 0, st, d, pair_faces, u, lam);
+  const size_t lds = 2 * sizeof(double) * (size_t)(max_na + 4) * (size_t)(kExchangeRows + 4);
+  hipLaunchKernelGGL(k_exchange, dim3((max_nb + kExchangeRows - 1) / kExchangeRows, n_pairs), dim3(kExThreads), lds, st, d,
+                     pair_faces, u, lam);
   return hipGetLastError();
 }
 

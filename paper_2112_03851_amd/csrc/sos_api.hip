@@ -69,7 +69,7 @@ struct sos_ctx {
   Seg seg;
   // workspaces
   double *u = nullptr, *f = nullptr, *lam = nullptr, *ut = nullptr, *rho = nullptr;
-  double* fsum = nullptr;  // sum of the Robin data at every boundary-shell node
+  double* b = nullptr;  // local right-hand side f_s + sum_j R_sj^T lambda_{s<-j}
   void *r = nullptr, *x = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   void *r1 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr;  // fused CG only
   double* part = nullptr;       // 3 per segmented block
@@ -117,7 +117,7 @@ void release(sos_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
   for (auto e : c->gevents) hipEventDestroy(e);
-  void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->fsum,
+  void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_cnt, c->team_part,
                   c->scal, c->ndone, c->counters};
@@ -406,11 +406,17 @@ FusedArgs fused_args(sos_ctx* c) {
   return a;
 }
 
+// b = f on every node; the face-sum kernel, run before every residual, then
+// adds the Robin data on the boundary shell (b = f + sum_j R^T lambda there).
+hipError_t copy_load_to_rhs(sos_ctx* c) {
+  return hipMemcpyAsync(c->b, c->f, c->n_local * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+}
+
 // One outer iteration in the batched form; ev (optional) brackets the fused kernel.
 int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
-  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->lam, c->fsum, st));
-  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->fsum, c->r, c->part,
+  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
+  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->b, c->r, c->part,
                          c->fused_team > 1 ? c->team_cnt : nullptr, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
@@ -423,8 +429,8 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
 int stepwise_iteration(sos_ctx* c) {
   hipStream_t st = c->stream;
   const SegLaunch& L = c->seg.L;
-  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->lam, c->fsum, st));
-  HIPCHK(launch_residual(c->dev, L, c->fp32, c->u, c->f, c->fsum, c->r, c->part, nullptr, st));
+  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
+  HIPCHK(launch_residual(c->dev, L, c->fp32, true, c->u, c->b, c->r, c->part, nullptr, st));
   HIPCHK(launch_cg_init(c->dev, L, c->part, c->opts.inner_tol, c->opts.inner_abs, c->scal, c->ndone, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.timing) {
@@ -629,8 +635,8 @@ int autotune(sos_ctx* c) {
       bool ok = true;
       for (int rep = 0; rep < 2 && ok; ++rep) {
         HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
-        HIPCHK(launch_face_sum(c->dev, c->max_shell, c->lam, c->fsum, st));
-        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, c->u, c->f, c->fsum, c->r, c->part,
+        HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
+        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->b, c->r, c->part,
                                team > 1 ? c->team_cnt : nullptr, st));
         HIPCHK(hipEventRecord(e0, st));
         if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
@@ -872,7 +878,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
       (rc = dalloc(&c->d_pairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||
       (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
       (rc = dalloc(&c->u, c->n_local)) || (rc = dalloc(&c->f, c->n_local)) || (rc = dalloc(&c->lam, c->n_lam)) ||
-      (rc = dalloc(&c->fsum, c->n_local)) ||
+      (rc = dalloc(&c->b, c->n_local)) ||
       (rc = dalloc(&c->ut, c->n_local)) || (rc = dalloc(&c->rho, c->n_local)) ||
       (rc = dalloc_v(&c->r, c->n_local * es)) || (rc = dalloc_v(&c->x, c->n_local * es)) ||
       (rc = dalloc_v(&c->p0, c->n_local * es)) || (rc = dalloc_v(&c->p1, c->n_local * es)) ||
@@ -920,7 +926,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
   if (e == hipSuccess)
     e = hipMemcpy(c->seg.d_bfirst, c->seg.bfirst.data(), c->seg.bfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->f, 0, c->n_local * sizeof(double));
-  if (e == hipSuccess) e = hipMemset(c->fsum, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->b, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->u, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->lam, 0, std::max<int64_t>(1, c->n_lam) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->ut, 0, c->n_local * sizeof(double));
@@ -1003,6 +1009,7 @@ int sos_layout(const sos_ctx* c, int32_t* n_sub, int64_t* offsets, int32_t* dims
 int sos_set_density(sos_ctx* c, const double* drho) {
   if (!c || !drho) return fail(SOS_EINVAL, "NULL argument");
   HIPCHK(launch_load_density(c->dev, c->max_n, drho, c->opts.G, c->f, c->stream));
+  HIPCHK(copy_load_to_rhs(c));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->have_load = true;
   return SOS_OK;
@@ -1011,6 +1018,7 @@ int sos_set_density(sos_ctx* c, const double* drho) {
 int sos_solve(sos_ctx* c, const double* drho, double tol, double* phi, sos_stats* stats) {
   if (!c || !drho) return fail(SOS_EINVAL, "NULL argument");
   HIPCHK(launch_load_density(c->dev, c->max_n, drho, c->opts.G, c->f, c->stream));
+  HIPCHK(copy_load_to_rhs(c));
   c->have_load = true;
   return solve_common(c, tol, phi, stats);
 }
@@ -1018,6 +1026,7 @@ int sos_solve(sos_ctx* c, const double* drho, double tol, double* phi, sos_stats
 int sos_solve_load(sos_ctx* c, const double* fn, double tol, double* phi, sos_stats* stats) {
   if (!c || !fn) return fail(SOS_EINVAL, "NULL argument");
   HIPCHK(launch_load_nodes(c->dev, c->max_n, fn, c->f, c->stream));
+  HIPCHK(copy_load_to_rhs(c));
   c->have_load = true;
   return solve_common(c, tol, phi, stats);
 }
@@ -1030,6 +1039,7 @@ int sos_adjoint(sos_ctx* c, const double* gphi, double tol, double* grad, double
     out = c->psi;
   }
   HIPCHK(launch_load_nodes(c->dev, c->max_n, gphi, c->f, c->stream));
+  HIPCHK(copy_load_to_rhs(c));
   c->have_load = true;
   int rc = solve_common(c, tol, out, stats);
   if (rc != SOS_OK && rc != SOS_ENOCONV) return rc;

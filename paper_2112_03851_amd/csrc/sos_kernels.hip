@@ -479,10 +479,10 @@ __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int
 // ---------------------------------------------------------------------------- outer kernels
 
 // r = f + sum_F R^T lambda_F - A u, rounded to TO; partials (r'D^-1 r, r'r, b'b).
-// g = sum_j R_sj^T lambda_{s<-j} on the boundary shell of every subdomain
-// (each shell node written once; nodes off the shell are never written and
-// stay zero).
-__global__ void k_face_sum(Dev d, const double* __restrict__ lam, double* __restrict__ g) {
+// b = f + sum_j R_sj^T lambda_{s<-j} on the boundary shell of every subdomain
+// (each shell node written once; off the shell b = f is left as it is).
+__global__ void k_face_sum(Dev d, const double* __restrict__ f, const double* __restrict__ lam,
+                           double* __restrict__ b) {
   const SubDesc sd = d.subs[blockIdx.y];
   const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2];
   const int xs = nx > 1 ? 2 : 1, ys = ny > 1 ? 2 : 1, zs = nz > 1 ? 2 : 1;
@@ -509,20 +509,16 @@ __global__ void k_face_sum(Dev d, const double* __restrict__ lam, double* __rest
     return;
   }
   const LamOff L = lam_offsets(d, sd);
-  g[sd.off + i + (int64_t)nx * (j + (int64_t)ny * k)] = lam_terms(L, lam, i, j, k, nx, ny, nz);
+  const int64_t idx = sd.off + i + (int64_t)nx * (j + (int64_t)ny * k);
+  b[idx] = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
 }
 
-template <typename T>
-struct Three {
-  T a, b, c;
-};
-
-// r = f + g - A u with g = sum_j R_sj^T lambda_{s<-j} (the face sums).
-template <typename TO, int CPT, bool Q>
+// r = b - A u, b = f + sum_j R_sj^T lambda_{s<-j} (from k_face_sum); RZ:
+// also r'D^-1 r (the stepwise CG's first gamma).
+template <typename TO, int CPT, bool Q, bool RZ>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
-                                                   const double* __restrict__ f, const double* __restrict__ g,
-                                                   TO* __restrict__ r, double* __restrict__ part,
-                                                   unsigned* __restrict__ team_cnt) {
+                                                   const double* __restrict__ b, TO* __restrict__ r,
+                                                   double* __restrict__ part, unsigned* __restrict__ team_cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* lds = reinterpret_cast<double*>(smem);
   // the fused kernel that follows counts its team barriers from zero
@@ -536,19 +532,19 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const double* __restrict__ ub = u + sl.off;
-  const double* __restrict__ fb = f + sl.off;
-  const double* __restrict__ gb = g + sl.off;
+  const double* __restrict__ bb = b + sl.off;
   TO* __restrict__ rb = r + sl.off;
-  auto fetch = [=](uint32_t li) { return Three<double>{at(ub, li), at(fb, li), at(gb, li)}; };
-  auto make = [](const Three<double>& v, uint32_t, bool, double) { return OpCarry<double>{v.a, v.b + v.c}; };
-  auto store = [&](uint32_t li, bool en, int, int, int, double q, double b, double dinv) {
+  auto fetch = [=](uint32_t li) { return Pair<double>{at(ub, li), at(bb, li)}; };
+  auto make = [](const Pair<double>& v, uint32_t, bool, double) { return OpCarry<double>{v.a, v.b}; };
+  auto store = [&](uint32_t li, bool en, int, int, int, double q, double bv, double dinv) {
     if (!en) return;
-    const TO rt = TO(b - q);
+    const TO rt = TO(bv - q);
     at(rb, li) = rt;
     const double rd = double(rt);
-    a0 += rd * rd * dinv;
+    if constexpr (RZ) a0 += rd * rd * dinv;
+    else (void)dinv;
     a1 += rd * rd;
-    a2 += b * b;
+    a2 += bv * bv;
   };
   zmarch(sl, lds, fetch, make, store);
   double acc[3] = {a0, a1, a2};
@@ -1367,21 +1363,28 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
   return hipGetLastError();
 }
 
-hipError_t launch_face_sum(const Dev& d, int max_shell, const double* lam, double* g, hipStream_t st) {
+hipError_t launch_face_sum(const Dev& d, int max_shell, const double* f, const double* lam, double* b,
+                           hipStream_t st) {
   if (max_shell <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_face_sum, dim3((max_shell + 255) / 256, d.geo.n_sub), dim3(256), 0, st, d, lam, g);
+  hipLaunchKernelGGL(k_face_sum, dim3((max_shell + 255) / 256, d.geo.n_sub), dim3(256), 0, st, d, f, lam, b);
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, const double* u, const double* f,
-                           const double* lam, void* r_out, double* part, unsigned* team_cnt, hipStream_t st) {
+hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u, const double* b,
+                           void* r_out, double* part, unsigned* team_cnt, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
-  if (fp32) {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
-                                               st, d, L.blocks, u, f, lam, (float*)r_out, part, team_cnt));
+  if (fp32 && rz) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_cnt));
+  } else if (fp32) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_cnt));
+  } else if (rz) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_cnt));
   } else {
-    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
-                                               st, d, L.blocks, u, f, lam, (double*)r_out, part, team_cnt));
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_cnt));
   }
   });
   return hipGetLastError();

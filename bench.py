@@ -43,16 +43,21 @@ def baseline_metric():
         return "Schwarz solves/s to 1e-8 rel residual"
 
 
-def measured_traffic(launch_bytes):
-    """HBM bytes per fused-kernel launch from committed rocprofv3 counters,
-    if they were taken on the current kernel source."""
+def measured_traffic(launch_bytes, st):
+    """HBM bytes per fused-kernel launch from committed rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, each scaled by its reading for a plain copy),
+    if they were taken on the current kernel source with the same block shape;
+    per launch of this run (the counters' ratio to the algorithmic bytes)."""
     try:
         pmc = json.load(open(PMC_FILE))
     except Exception:
         return None
     if pmc.get("kernel_sha") != kernel_sha():
         return None
-    return pmc.get("traffic_bytes_per_launch")
+    if (pmc.get("block"), pmc.get("cols_per_thread"), pmc.get("team")) != (st["block"], st["cols_per_thread"],
+                                                                           st["team"]):
+        return None
+    return pmc["traffic_over_algorithmic"] * launch_bytes
 
 
 def cpu_baseline(wl, budget_s, phi_gpu):
@@ -109,6 +114,20 @@ def cpu_baseline(wl, budget_s, phi_gpu):
     return out
 
 
+def reference_copy(torch, mib):
+    """A plain device-to-device copy of known size (profiling runs only): what
+    the memory counters read for it scales their reading of the solver's kernels."""
+    if mib <= 0:
+        return
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {n * 4} bytes device to device (one read and one write of each byte)", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +145,9 @@ def main():
     ap.add_argument("--profile-outer", type=int, default=0,
                     help="profiling only: run one batched solve of this many outer iterations "
                          "(no convergence, no JSON line) for rocprofv3 counter collection")
+    ap.add_argument("--profile-copy-mib", type=int, default=0,
+                    help="profiling only: finally copy a buffer of this many MiB device to device, "
+                         "the reference for scaling the memory counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -147,6 +169,7 @@ def main():
         print(f"profiled {st['outer_iters']} outer iterations, {st['kernel_launches']} fused launches, "
               f"{st['kernel_bytes'] / st['kernel_launches']:.0f} algorithmic bytes per launch, "
               f"{st['kernel_ms'] / st['kernel_launches']:.4f} ms per launch", flush=True)
+        reference_copy(torch, args.profile_copy_mib)
         return
     prob = Problem(wl.ne, wl.lengths, wl.bc, cuts=wl.cuts, p=wl.p, G=wl.G, precision="fp32", mode="batched",
                    check_every=args.check_every, inner_tol=args.inner_tol, timing=1, block=args.block,
@@ -169,7 +192,7 @@ def main():
     launch_s = tot["kernel_ms"] * 1e-3 / tot["kernel_launches"]
     achieved = launch_bytes / launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes, st),
                 "kernel": "k_fused_cg<float>", "avg_launch_ms": launch_s * 1e3,
                 "algorithmic_bytes_per_launch": launch_bytes}
     batched = {"outer_iters": tot["outer_iters"] // args.steps, "inner_iters": tot["inner_iters"] // args.steps,
@@ -209,6 +232,7 @@ def main():
         "cpu_baseline": cpu, "kernel_sha": kernel_sha(),
     }
     print(json.dumps(line), flush=True)
+    reference_copy(torch, args.profile_copy_mib)
 
 
 if __name__ == "__main__":

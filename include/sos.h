@@ -145,6 +145,36 @@ int sos_opts_default(sos_opts* opts, int32_t precision);
 int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* robin,
               const sos_opts* opts, sos_ctx** out);
 
+/* Batch of `copies` independent copies of the same problem in one context
+ * (1 <= copies <= 4096), for evaluating many transmission conditions at once
+ * (the stochastic search of Sec. 4 scores candidate coefficients by the
+ * convergence of the Schwarz iteration; Sec. 5 runs such evaluations on the
+ * GPU). Copy c holds subdomains c*n_sub .. (c+1)*n_sub - 1 and directed faces
+ * c*n_faces .. in the order of one copy; robin->p / robin->q, when given,
+ * hold copies*n_faces values in that order (a different condition per copy).
+ * Every kernel launch covers all copies. Vectors (local layout, lambda) and
+ * phi_nodes (copies * nodes, copy-major) are concatenated copy after copy;
+ * drho_elem is one field shared by every copy. The stopping quantity of a
+ * solve is the largest relative residual over the copies. sos_solve_load and
+ * sos_adjoint return SOS_EINVAL on such a context. sos_setup is
+ * sos_setup_batch with copies = 1. */
+int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t copies,
+                    const sos_robin* robin, const sos_opts* opts, sos_ctx** out);
+
+/* Relative residual ||f - K u~|| / ||f|| of every copy at the last global
+ * residual evaluation (host memory, copies values). */
+int sos_batch_residuals(sos_ctx* ctx, double* res);
+
+/* Convergence rate of every copy: loads drho, starts from u = 0, lambda = 0,
+ * runs n_first outer iterations, records each copy's relative residual r1,
+ * runs to n_second and records r2; rates[c] = (r2/r1)^(1/(n_second-n_first))
+ * (NaN if not finite). best = the copy of the smallest finite rate (ties: the
+ * lower index). res_first / res_second / best / stats may be NULL; host
+ * memory. SOS_EBREAKDOWN if no rate is finite. */
+int sos_batch_rates(sos_ctx* ctx, const double* drho_elem, int32_t n_first, int32_t n_second,
+                    double* rates, double* res_first, double* res_second, int32_t* best,
+                    sos_stats* stats);
+
 /* Replace the Robin coefficients (same partition). */
 int sos_set_robin(sos_ctx* ctx, const sos_robin* robin);
 

@@ -111,6 +111,7 @@ int64_t align64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
 constexpr int kStallOuter = 2000;  // outer iterations without 1% progress
 constexpr int kMaxTeam = 8;        // blocks per subdomain in the fused kernel
+constexpr int kMaxCopies = 4096;   // independent problem copies of one context
 
 void release(sos_ctx* c) {
   if (!c) return;
@@ -376,7 +377,7 @@ int enqueue_check(sos_ctx* c, double* phi) {
   HIPCHK(launch_glue(c->dev, c->max_n, c->u, c->ut, st));
   HIPCHK(launch_local_residual(c->dev, c->seg.L, c->ut, c->f, c->rho, st));
   HIPCHK(launch_assemble_norm(c->dev, c->max_n, c->rho, c->f, c->ut, phi, c->part_norm, st));
-  HIPCHK(launch_final_norm(c->part_norm, c->n_norm_blocks, c->d_res, c->d_hres, st));
+  HIPCHK(launch_final_norm(c->part_norm, c->n_norm_blocks, c->geo.copies, c->d_res, c->d_hres, st));
   return SOS_OK;
 }
 
@@ -717,9 +718,15 @@ int sos_opts_default(sos_opts* o, int32_t precision) {
 
 int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* robin, const sos_opts* opts,
               sos_ctx** out) {
+  return sos_setup_batch(mesh, part, 1, robin, opts, out);
+}
+
+int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t copies, const sos_robin* robin,
+                    const sos_opts* opts, sos_ctx** out) {
   if (!out) return fail(SOS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mesh || !part || !robin || !opts) return fail(SOS_EINVAL, "NULL argument");
+  if (copies < 1 || copies > kMaxCopies) return fail(SOS_EINVAL, "copies must be in [1, %d]", kMaxCopies);
   int rc = check_opts(opts);
   if (rc) return rc;
   bool any_dir = false;
@@ -837,6 +844,44 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
     F.opp = dj.face[2 * F.axis + (1 - F.side)];
     if (F.s < F.j) c->pairs.push_back((int32_t)(&F - &c->faces[0]));
   }
+  // independent copies of the problem: subdomains, faces and vectors repeat
+  // copy after copy (copy c's subdomain s is c * n_sub + s)
+  {
+    const int ns = g.n_sub, nf = (int)c->faces.size(), np = (int)c->pairs.size();
+    const int64_t nl = c->n_local, nlam = c->n_lam;
+    if ((int64_t)ns * copies > INT32_MAX / 2 || (int64_t)nf * copies > INT32_MAX / 2) {
+      release(c);
+      return fail(SOS_EINVAL, "too many subdomains in %d copies", copies);
+    }
+    for (auto& d : c->subs) d.copy = d.sbase = 0;
+    c->subs.resize((size_t)ns * copies);
+    c->faces.resize((size_t)nf * copies);
+    for (int cc = 1; cc < copies; ++cc) {
+      for (int s = 0; s < ns; ++s) {
+        SubDesc d = c->subs[s];
+        d.off += cc * nl;
+        d.copy = cc;
+        d.sbase = cc * ns;
+        for (int f = 0; f < 6; ++f)
+          if (d.face[f] >= 0) d.face[f] += cc * nf;
+        c->subs[(size_t)cc * ns + s] = d;
+      }
+      for (int f = 0; f < nf; ++f) {
+        FaceDesc F = c->faces[f];
+        F.s += cc * ns;
+        F.j += cc * ns;
+        F.opp += cc * nf;
+        F.lam_off += cc * nlam;
+        c->faces[(size_t)cc * nf + f] = F;
+      }
+      for (int p = 0; p < np; ++p) c->pairs.push_back(c->pairs[p] + cc * nf);
+    }
+    c->n_local = nl * copies;
+    c->n_lam = nlam * copies;
+    c->n_nodes *= copies;
+    g.n_sub = ns * copies;
+    g.copies = copies;
+  }
   rc = apply_robin(c, robin);
   if (rc) {
     release(c);
@@ -885,7 +930,7 @@ int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* 
       (rc = dalloc_v(&c->q, c->n_local * es)) || (rc = dalloc_v(&c->r1, c->n_local * es)) ||
       (rc = dalloc_v(&c->w1, c->n_local * es)) || (rc = dalloc_v(&c->s0, c->n_local * es)) ||
       (rc = dalloc_v(&c->s1, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
-      (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4)) ||
+      (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4 + (size_t)copies)) ||
       (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2)) ||
       (rc = dalloc(&c->team_cnt, c->subs.size())) || (rc = dalloc(&c->team_part, c->subs.size() * kMaxTeam * 2 * 4))) {
     release(c);
@@ -1015,6 +1060,55 @@ int sos_set_density(sos_ctx* c, const double* drho) {
   return SOS_OK;
 }
 
+int sos_batch_residuals(sos_ctx* c, double* res) {
+  if (!c || !res) return fail(SOS_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(res, c->d_res + 3, (size_t)c->geo.copies * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SOS_OK;
+}
+
+int sos_batch_rates(sos_ctx* c, const double* drho, int32_t n_first, int32_t n_second, double* rates,
+                    double* res_first, double* res_second, int32_t* best, sos_stats* stats) {
+  if (!c || !drho || !rates) return fail(SOS_EINVAL, "NULL argument");
+  if (n_first < 1 || n_second <= n_first) return fail(SOS_EINVAL, "need 1 <= n_first < n_second");
+  const int B = c->geo.copies;
+  HIPCHK(launch_load_density(c->dev, c->max_n, drho, c->opts.G, c->f, c->stream));
+  HIPCHK(copy_load_to_rhs(c));
+  c->have_load = true;
+  int rc = reset_state(c);
+  if (rc) return rc;
+  if (c->opts.mode == SOS_BATCHED && (rc = autotune(c))) return rc;
+  bool conv = false;
+  std::vector<double> r1(B), r2(B);
+  sos_stats s1{}, s2{};
+  if ((rc = run_outer(c, 0.0, n_first, &s1, &conv)) || (rc = sos_batch_residuals(c, r1.data()))) return rc;
+  if ((rc = run_outer(c, 0.0, n_second - n_first, &s2, &conv)) || (rc = sos_batch_residuals(c, r2.data())))
+    return rc;
+  int arg = -1;
+  for (int i = 0; i < B; ++i) {
+    // rate per outer iteration between the two checks
+    rates[i] = (r1[i] > 0.0 && std::isfinite(r1[i]) && std::isfinite(r2[i]))
+                   ? std::pow(r2[i] / r1[i], 1.0 / double(n_second - n_first))
+                   : NAN;
+    if (res_first) res_first[i] = r1[i];
+    if (res_second) res_second[i] = r2[i];
+    if (std::isfinite(rates[i]) && (arg < 0 || rates[i] < rates[arg])) arg = i;  // ties: the lower index
+  }
+  if (best) *best = arg;
+  if (stats) {
+    *stats = s2;
+    stats->outer_iters = s1.outer_iters + s2.outer_iters;
+    stats->checks = s1.checks + s2.checks;
+    stats->inner_iters = s1.inner_iters + s2.inner_iters;
+    stats->seconds = s1.seconds + s2.seconds;
+    stats->kernel_ms = s1.kernel_ms + s2.kernel_ms;
+    stats->kernel_launches = s1.kernel_launches + s2.kernel_launches;
+    stats->kernel_bytes = s1.kernel_bytes + s2.kernel_bytes;
+  }
+  return arg < 0 ? fail(SOS_EBREAKDOWN, "no copy has a finite rate") : SOS_OK;
+}
+
 int sos_solve(sos_ctx* c, const double* drho, double tol, double* phi, sos_stats* stats) {
   if (!c || !drho) return fail(SOS_EINVAL, "NULL argument");
   HIPCHK(launch_load_density(c->dev, c->max_n, drho, c->opts.G, c->f, c->stream));
@@ -1025,6 +1119,7 @@ int sos_solve(sos_ctx* c, const double* drho, double tol, double* phi, sos_stats
 
 int sos_solve_load(sos_ctx* c, const double* fn, double tol, double* phi, sos_stats* stats) {
   if (!c || !fn) return fail(SOS_EINVAL, "NULL argument");
+  if (c->geo.copies > 1) return fail(SOS_EINVAL, "nodal loads are not supported on a context of several copies");
   HIPCHK(launch_load_nodes(c->dev, c->max_n, fn, c->f, c->stream));
   HIPCHK(copy_load_to_rhs(c));
   c->have_load = true;
@@ -1033,6 +1128,7 @@ int sos_solve_load(sos_ctx* c, const double* fn, double tol, double* phi, sos_st
 
 int sos_adjoint(sos_ctx* c, const double* gphi, double tol, double* grad, double* psi, sos_stats* stats) {
   if (!c || !gphi || !grad) return fail(SOS_EINVAL, "NULL argument");
+  if (c->geo.copies > 1) return fail(SOS_EINVAL, "the adjoint is not supported on a context of several copies");
   double* out = psi;
   if (!out) {
     if (!c->psi && dalloc(&c->psi, (size_t)c->n_nodes)) return SOS_ENOMEM;

@@ -25,6 +25,8 @@ struct SubDesc {
   double ehi[3];    // Robin coefficient at closure node ne2 per axis
   double qlo[3];    // second-order coefficient q at closure node 0 per axis (0 if none)
   double qhi[3];    // second-order coefficient q at closure node ne2 per axis
+  int32_t copy;     // index of the problem copy this subdomain belongs to (batched copies)
+  int32_t sbase;    // index of that copy's first subdomain
 };
 
 // One directed face (s <- j).
@@ -45,7 +47,8 @@ struct Geom {
   int32_t ne[3];
   int32_t nn[3];     // global nodes per axis (2ne+1)
   int32_t nparts[3];
-  int32_t n_sub;
+  int32_t n_sub;      // subdomains of all copies
+  int32_t copies;     // independent copies of the problem (1 unless batched)
   int32_t bc[6];
 };
 

@@ -111,8 +111,9 @@ hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, cons
                                 const double* ut, double* phi, double* part, hipStream_t st);
 // Number of partials (pairs) written by launch_assemble_norm.
 int assemble_blocks(const Dev& d, int max_n);
-// res = sqrt(sum rr / sum ff) -> dev_out[0], host_out[0] (host-mapped, may be null).
-hipError_t launch_final_norm(const double* part, int32_t nblk, double* dev_out, double* host_out,
+// Per copy res_c = sqrt(sum rr / sum ff) -> dev_out[3 + c]; the largest over
+// the copies -> dev_out[0] and host_out[0] (host-mapped, may be null).
+hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, double* dev_out, double* host_out,
                              hipStream_t st);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st);
 // grad_e = 4 pi G sum_a psi_a int_e phi_a for every element (psi over all nodes).

@@ -1153,7 +1153,7 @@ __device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i
   for (int cz = 0; cz < nc[2]; ++cz)
     for (int cy = 0; cy < nc[1]; ++cy)
       for (int cx = 0; cx < nc[0]; ++cx) {
-        const int s2 = (p0[0] + cx) + Px * ((p0[1] + cy) + Py * (p0[2] + cz));
+        const int s2 = sd.sbase + (p0[0] + cx) + Px * ((p0[1] + cy) + Py * (p0[2] + cz));
         const SubDesc& o = d.subs[s2];
         const int ix = cx ? i1[0] : i0[0], iy = cy ? i1[1] : i0[1], iz = cz ? i1[2] : i0[2];
         fn(o.off + ix + (int64_t)o.n[0] * (iy + (int64_t)o.n[1] * iz));
@@ -1192,8 +1192,9 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
       acc[0] = rs * rs;
       acc[1] = fs * fs;
       if (phi) {
+        const int64_t nodes = (int64_t)d.geo.nn[0] * d.geo.nn[1] * d.geo.nn[2];
         const int64_t g = (sd.lo[0] + i) + (int64_t)d.geo.nn[0] * ((sd.lo[1] + j) + (int64_t)d.geo.nn[1] * (sd.lo[2] + k));
-        phi[g] = ut[sd.off + t];
+        phi[sd.copy * nodes + g] = ut[sd.off + t];
       }
     }
   }
@@ -1205,19 +1206,34 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
   }
 }
 
-__global__ void k_final_norm(const double* __restrict__ part, int nblk, double* dev_out, double* host_out) {
-  double acc[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    acc[0] += part[2 * b];
-    acc[1] += part[2 * b + 1];
-  }
-  block_sum(acc);
-  if (threadIdx.x == 0) {
+// Per copy (the assemble blocks of copy c are the contiguous range
+// [c nblk / copies, (c + 1) nblk / copies)): res_c = ||f - K u~|| / ||f||, and
+// the largest over the copies (the stopping quantity). dev_out: [max res,
+// r'r, f'f of the worst copy, res_0 .. res_{copies-1}].
+__global__ void k_final_norm(const double* __restrict__ part, int nblk, int copies, double* dev_out,
+                             double* host_out) {
+  const int per = nblk / copies;
+  double worst = 0.0, wr = 0.0, wf = 0.0;
+  for (int c = 0; c < copies; ++c) {
+    double acc[2] = {0.0, 0.0};
+    for (int b = c * per + threadIdx.x; b < (c + 1) * per; b += blockDim.x) {
+      acc[0] += part[2 * b];
+      acc[1] += part[2 * b + 1];
+    }
+    block_sum(acc);
     const double res = acc[1] > 0.0 ? sqrt(acc[0] / acc[1]) : (acc[0] > 0.0 ? INFINITY : 0.0);
-    dev_out[0] = res;
-    dev_out[1] = acc[0];
-    dev_out[2] = acc[1];
-    if (host_out) host_out[0] = res;
+    if (threadIdx.x == 0) dev_out[3 + c] = res;
+    if (c == 0 || !(res <= worst)) {  // NaN propagates
+      worst = res;
+      wr = acc[0];
+      wf = acc[1];
+    }
+  }
+  if (threadIdx.x == 0) {
+    dev_out[0] = worst;
+    dev_out[1] = wr;
+    dev_out[2] = wf;
+    if (host_out) host_out[0] = worst;
   }
 }
 
@@ -1507,8 +1523,9 @@ hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, cons
   return hipGetLastError();
 }
 
-hipError_t launch_final_norm(const double* part, int32_t nblk, double* dev_out, double* host_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, nblk, dev_out, host_out);
+hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, double* dev_out, double* host_out,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, nblk, copies, dev_out, host_out);
   return hipGetLastError();
 }
 

@@ -85,6 +85,11 @@ def lib():
         "sos_opts_default": (C.c_int, [C.POINTER(Opts), I]),
         "sos_setup": (C.c_int, [C.POINTER(Mesh), C.POINTER(Partition), C.POINTER(Robin), C.POINTER(Opts),
                                 C.POINTER(P)]),
+        "sos_setup_batch": (C.c_int, [C.POINTER(Mesh), C.POINTER(Partition), I, C.POINTER(Robin),
+                                      C.POINTER(Opts), C.POINTER(P)]),
+        "sos_batch_residuals": (C.c_int, [P, C.POINTER(D)]),
+        "sos_batch_rates": (C.c_int, [P, P, I, I, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(I),
+                                      C.POINTER(Stats)]),
         "sos_set_robin": (C.c_int, [P, C.POINTER(Robin)]),
         "sos_set_opts": (C.c_int, [P, C.POINTER(Opts)]),
         "sos_faces": (C.c_int, [P, C.POINTER(I), C.POINTER(I)]),
@@ -160,10 +165,12 @@ class Problem:
     q: second-order coefficient (0: zeroth-order operator p)
     precision: 'fp64' or 'fp32' (FP32 inner CG, FP64 outer)
     mode: 'stepwise' or 'batched'
+    copies: independent copies of the problem in one context (sos_setup_batch);
+            p and q may then also hold one value per copy
     """
 
     def __init__(self, ne, lengths=(1.0, 1.0, 1.0), bc=(0,) * 6, cuts=None, nparts=None, p=1.0,
-                 precision="fp64", mode=None, q=0.0, **opts):
+                 precision="fp64", mode=None, q=0.0, copies=1, **opts):
         L = lib()
         prec = SOS_FP32_INNER if precision in ("fp32", SOS_FP32_INNER) else SOS_FP64
         o = default_opts(prec)
@@ -189,17 +196,25 @@ class Problem:
                 part.nparts[a] = int(nparts[a])
                 part.cuts[a] = C.POINTER(C.c_int32)()
         self.part = part
-        self.n_faces = self._count_faces([int(part.nparts[a]) for a in range(3)])
-        self._robin = self._make_robin(p, self.n_faces, q)
+        self.copies = int(copies)
+        self.faces_per_copy = self._count_faces([int(part.nparts[a]) for a in range(3)])
+        self.n_faces = self.faces_per_copy * self.copies
+        self._robin = self._make_robin(self._per_face(p), self.n_faces, self._per_face(q))
         self.opts = o
         self.ne = tuple(int(v) for v in ne)
-        self.n_nodes = int(np.prod([2 * v + 1 for v in ne]))
+        self.n_nodes = int(np.prod([2 * v + 1 for v in ne])) * self.copies
         self.n_elem = int(np.prod(ne))
         h = C.c_void_p()
-        _check(L.sos_setup(C.byref(self.mesh), C.byref(part), C.byref(self._robin[0]), C.byref(o),
-                           C.byref(h)))
+        _check(L.sos_setup_batch(C.byref(self.mesh), C.byref(part), self.copies, C.byref(self._robin[0]),
+                                 C.byref(o), C.byref(h)))
         self.h = h
         self.precision = prec
+
+    def _per_face(self, v):
+        """A per-copy coefficient array expanded to one value per directed face."""
+        if np.ndim(v) != 0 and self.copies > 1 and len(v) == self.copies:
+            return np.repeat(np.asarray(v, float), self.faces_per_copy)
+        return v
 
     @staticmethod
     def _count_faces(P):
@@ -263,7 +278,7 @@ class Problem:
                 "lo": np.array(lo, np.int32).reshape(-1, 3), "face_off": np.array(foff, np.int64)}
 
     def set_robin(self, p, q=0.0):
-        self._robin = self._make_robin(p, self.n_faces, q)
+        self._robin = self._make_robin(self._per_face(p), self.n_faces, self._per_face(q))
         _check(lib().sos_set_robin(self.h, C.byref(self._robin[0])))
 
     def set_opts(self, **kw):
@@ -272,6 +287,25 @@ class Problem:
         _check(lib().sos_set_opts(self.h, C.byref(self.opts)))
 
     # ------------------------------------------------------------------ device calls
+    def batch_residuals(self):
+        """Relative residual of every copy at the last global residual check."""
+        out = (C.c_double * self.copies)()
+        _check(lib().sos_batch_residuals(self.h, out))
+        return np.array(out)
+
+    def batch_rates(self, drho, n_first=10, n_second=20):
+        """Convergence rate of every copy between outer iterations n_first and
+        n_second from a zero start: (rates, r_first, r_second, best copy, stats)."""
+        import torch
+        B = self.copies
+        rates, r1, r2 = (C.c_double * B)(), (C.c_double * B)(), (C.c_double * B)()
+        best = C.c_int32()
+        st = Stats()
+        _sync_torch()
+        _check(lib().sos_batch_rates(self.h, _ptr(drho, torch.float64), int(n_first), int(n_second), rates, r1, r2,
+                                     C.byref(best), C.byref(st)))
+        return np.array(rates), np.array(r1), np.array(r2), int(best.value), st.as_dict()
+
     def solve(self, drho, tol, phi=None):
         import torch
         phi = torch.empty(self.n_nodes, dtype=torch.float64, device=drho.device) if phi is None else phi

@@ -102,3 +102,14 @@ def random_widths(rng, total, parts, lo, hi, max_draws=100000):
 def widths_to_cuts(widths):
     """Interior cut positions (element indices) from a width vector."""
     return np.cumsum(np.asarray(widths, np.int64))[:-1]
+
+
+def robin_candidates(n, h, seed=0):
+    """Seeded candidate transmission coefficients for the batched search:
+    p log-uniform on [h^-3/2, 10/h], q uniform on [0, h] (a log-uniform law on
+    [0, h] does not exist). Returns (p, q), arrays of n values."""
+    rng = np.random.default_rng(seed)
+    lo, hi = np.log(h ** -1.5), np.log(10.0 / h)
+    p = np.exp(rng.uniform(lo, hi, size=n))
+    q = rng.uniform(0.0, h, size=n)
+    return p, q

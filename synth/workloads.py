@@ -13,6 +13,8 @@ job (the oracle on the CPU, the HIP library on the GPU).
   c4  unit cube, 48^3 elements, 3x3x3, top face z = 1 homogeneous Neumann,
       all other faces Dirichlet (the adjoint workload)
   c5  unit cube, 128^3 elements, 8x8x8 subdomains (the large batched solve)
+  c5copy  unit cube, 32^3 elements, 2x2x2 subdomains: the small copy on which
+      candidate transmission conditions are scored before the c5 solve
 
 The gravitational constant is the one the paper quotes in Sec. 2.
 """
@@ -112,6 +114,11 @@ def workload(name: str, seed: int = 0, **over) -> Workload:
         ne = (128, 128, 128)
         wl = Workload(name, ne, (1.0, 1.0, 1.0), dirichlet,
                       tuple(equal_cuts(128, 8) for _ in range(3)), 8.0 * 128, 1e-8, seed,
+                      density="crater", n_blobs=10)
+    elif name == "c5copy":
+        ne = (32, 32, 32)
+        wl = Workload(name, ne, (1.0, 1.0, 1.0), dirichlet,
+                      tuple(equal_cuts(32, 2) for _ in range(3)), 8.0 * 32, 1e-8, seed,
                       density="crater", n_blobs=10)
     else:
         raise KeyError(name)

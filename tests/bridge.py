@@ -30,7 +30,8 @@ class Case:
 
     def problem(self, **kw):
         from paper_2112_03851_amd.sos import Problem
-        return Problem(self.ne, self.lengths, self.bc, cuts=self.cuts, p=self.p, **kw)
+        kw.setdefault("p", self.p)
+        return Problem(self.ne, self.lengths, self.bc, cuts=self.cuts, **kw)
 
     def check_layout(self, prob):
         lay = prob.layout()

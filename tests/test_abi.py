@@ -40,6 +40,10 @@ def test_opts_defaults():
     (dict(ne=(4, 4, 4), nparts=(2, 1, 1), check_every=0), "check_every"),
     (dict(ne=(4, 4, 4), nparts=(2, 1, 1), block=100), "block"),
     (dict(ne=(4, 4, 4), nparts=(2, 1, 1), inner_tol=0.0, inner_abs=0.0), "inner_tol"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=0), "copies"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=5000), "copies"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=3, p=[1.0, 0.0, 2.0]), "Robin"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=2, p=1.0, q=[0.0, -1.0]), "second-order"),
 ])
 def test_invalid_arguments_rejected_on_the_host(kw, msg):
     with pytest.raises(sos.SosError) as ei:

@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -128,6 +130,55 @@ def reference_copy(torch, mib):
     print(f"copied {n * 4} bytes device to device (one read and one write of each byte)", flush=True)
 
 
+def candidate_pipeline(args, torch, Problem, workload):
+    """Stochastic transmission-condition search at scale: seeded candidates
+    (p log-uniform on [h^-3/2, 10/h], q uniform on [0, h], h of the copy)
+    scored by their convergence rate between outer iterations 10 and 20 on the
+    32^3 copy, all candidates in one context; the best moves to the 128^3 mesh
+    with p h and q / h kept (both meshes have 16^3-element subdomains) and is
+    solved to 1e-8, next to the prescribed zeroth-order p = 8/h."""
+    from synth.generators import robin_candidates
+    small, big = workload("c5copy", seed=args.seed), workload("c5", seed=args.seed)
+    h, H = small.lengths[0] / small.ne[0], big.lengths[0] / big.ne[0]
+    p, q = robin_candidates(args.candidates, h, seed=args.seed)
+    d_small = torch.tensor(small.drho(), device="cuda")
+    prob = Problem(small.ne, small.lengths, small.bc, cuts=small.cuts, p=p, q=q, G=small.G, precision="fp32",
+                   mode="batched", check_every=10, inner_tol=args.inner_tol, copies=args.candidates)
+    prob.batch_rates(d_small, 10, 20)  # first call tunes the block shape
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rates, r1, r2, best, st = prob.batch_rates(d_small, 10, 20)
+    torch.cuda.synchronize()
+    t_score = time.perf_counter() - t0
+    prob.close()
+    pb, qb = p[best] * h / H, q[best] * H / h
+    d_big = torch.tensor(big.drho(), device="cuda")
+    out = {}
+    for name, pp, qq in (("transferred_best", pb, qb), ("prescribed_p_8_over_h", big.p, 0.0)):
+        pr = Problem(big.ne, big.lengths, big.bc, cuts=big.cuts, p=pp, q=qq, G=big.G, precision="fp32",
+                     mode="batched", check_every=args.check_every, inner_tol=args.inner_tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s = pr.solve(d_big, big.tol)
+        torch.cuda.synchronize()
+        out[name] = {"p": pp, "q": qq, "seconds": time.perf_counter() - t0, "outer_iters": s["outer_iters"],
+                     "inner_iters": s["inner_iters"], "rel_residual": s["rel_residual"], "converged": s["converged"],
+                     "block": s["block"], "cols_per_thread": s["cols_per_thread"], "team": s["team"]}
+        pr.close()
+    line = {"metric": "candidate scoring on the 32^3 copy + 128^3 solve to 1e-8 with the best condition",
+            "value": t_score, "unit": "s (scoring all candidates)", "n_gpus": 1, "higher_is_better": False,
+            "data": "synthetic", "dtype": "f32+f64",
+            "config": {"workload": f"{args.candidates} candidates x 8 subdomains of the 32^3 copy (one context, "
+                                   f"{args.candidates * 8} subdomains per launch), 20 outer iterations; then 128^3, "
+                                   f"8x8x8 subdomains, crater-like anomaly seed {args.seed}"},
+            "scoring": {"outer_iters": st["outer_iters"], "inner_iters": st["inner_iters"], "best": best,
+                        "best_rate": float(rates[best]), "p_best": float(p[best]), "q_best": float(q[best]),
+                        "rate_range": [float(np.nanmin(rates)), float(np.nanmax(rates))],
+                        "block": st["block"], "team": st["team"]},
+            "solves": out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +196,9 @@ def main():
     ap.add_argument("--profile-outer", type=int, default=0,
                     help="profiling only: run one batched solve of this many outer iterations "
                          "(no convergence, no JSON line) for rocprofv3 counter collection")
+    ap.add_argument("--candidates", type=int, default=0,
+                    help="instead of the default line: score this many seeded (p, q) candidates on the 32^3 copy "
+                         "(all copies in every launch), transfer the best to the 128^3 workload and solve it")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="profiling only: finally copy a buffer of this many MiB device to device, "
                          "the reference for scaling the memory counters")
@@ -159,6 +213,9 @@ def main():
     from paper_2112_03851_amd.sos import Problem
     from synth import workload
 
+    if args.candidates:
+        candidate_pipeline(args, torch, Problem, workload)
+        return
     wl = workload(args.workload, seed=args.seed)
     drho = torch.tensor(wl.drho(), device="cuda")
     if args.profile_outer:

@@ -59,20 +59,24 @@ def blobs_density(ne, lengths=(1.0, 1.0, 1.0), n_blobs=3, seed=0):
     return _eval_blobs(element_centroids(ne, lengths), blobs)
 
 
-def crater_density(ne, lengths=(1.0, 1.0, 1.0), seed=0, n_blobs=10):
+def crater_density(ne, lengths=(1.0, 1.0, 1.0), seed=0, n_blobs=10, up=2):
     """Layered medium with a buried crater-like ring and random blobs.
 
-    * three horizontal layers of equal thickness in z, each +-50 kg/m^3 with
-      its sign drawn first (3 draws of integers(0, 2), bottom layer first);
+    * three horizontal layers of equal thickness along the vertical axis `up`
+      (z by default), each +-50 kg/m^3 with its sign drawn first (3 draws of
+      integers(0, 2), bottom layer first);
     * a cylindrical ring 0.15 <= r <= 0.3 around the vertical axis through the
-      box centre (r measured in units of the x length), occupying the top 0.2
+      box centre (r in units of the horizontal lengths), occupying the top 0.2
       of the box height, of -300 kg/m^3;
-    * n_blobs Gaussian blobs drawn after the layer signs (see blob_params).
+    * n_blobs Gaussian blobs drawn after the layer signs (see blob_params),
+      their centres drawn in the frame whose third axis is vertical.
     """
     rng = np.random.default_rng(seed)
     signs = 1.0 - 2.0 * rng.integers(0, 2, size=3)
+    order = [a for a in range(3) if a != up] + [up]   # horizontal, horizontal, vertical
+    lengths = tuple(float(lengths[a]) for a in order)
     blobs = blob_params(rng, n_blobs, lengths)
-    xyz = element_centroids(ne, lengths)
+    xyz = element_centroids(ne, [lengths[order.index(a)] for a in range(3)])[:, order]
     Lx, Ly, Lz = (float(v) for v in lengths)
     layer = np.minimum((xyz[:, 2] / Lz * 3.0).astype(int), 2)
     out = 50.0 * signs[layer]

@@ -15,6 +15,13 @@ job (the oracle on the CPU, the HIP library on the GPU).
   c5  unit cube, 128^3 elements, 8x8x8 subdomains (the large batched solve)
   c5copy  unit cube, 32^3 elements, 2x2x2 subdomains: the small copy on which
       candidate transmission conditions are scored before the c5 solve
+  slab32 / slab64 / slab128  the shape of the paper's Sec. 6 runs: a
+      250 x 250 x 15 box (scaled to 1 x 1 x 0.06) cut into 32, 64 or 128
+      slabs along x, crater-like field with the thin axis vertical, tol 1e-6;
+      stored with the thin axis as y (320 x 19 x 320 elements, 16.0 M nodes)
+      so every slab's x-y node plane stays small. Robin coefficients: the
+      second-order symmetric condition from the Fourier optimisation over the
+      interface's frequency range (extra["kmin"], extra["kmax"])
 
 The gravitational constant is the one the paper quotes in Sec. 2.
 """
@@ -46,6 +53,7 @@ class Workload:
     density: str = "blobs"
     n_blobs: int = 3
     extra: dict = field(default_factory=dict)
+    up: int = 2  # vertical axis of the crater-like field
 
     @property
     def h(self):
@@ -72,7 +80,7 @@ class Workload:
         if self.density == "blobs":
             return blobs_density(self.ne, self.lengths, self.n_blobs, self.seed)
         if self.density == "crater":
-            return crater_density(self.ne, self.lengths, self.seed, self.n_blobs)
+            return crater_density(self.ne, self.lengths, self.seed, self.n_blobs, self.up)
         raise ValueError(self.density)
 
 
@@ -120,6 +128,19 @@ def workload(name: str, seed: int = 0, **over) -> Workload:
         wl = Workload(name, ne, (1.0, 1.0, 1.0), dirichlet,
                       tuple(equal_cuts(32, 2) for _ in range(3)), 8.0 * 32, 1e-8, seed,
                       density="crater", n_blobs=10)
+    elif name in ("slab32", "slab64", "slab128"):
+        parts = int(name[4:])
+        ne = (320, 19, 320)
+        lengths = (1.0, 0.06, 1.0)
+        widths = [320 // parts + (1 if k < 320 % parts else 0) for k in range(parts)]
+        cuts = (tuple(int(v) for v in np.cumsum(widths)[:-1]), (), ())
+        hy, hz = lengths[1] / ne[1], lengths[2] / ne[2]
+        # tangential modes of an x-interface (Dirichlet edges): the lowest
+        # sin(pi y / Ly) sin(pi z / Lz), the highest at the node spacing h/2
+        kmin = float(np.pi * np.hypot(1.0 / lengths[1], 1.0 / lengths[2]))
+        kmax = float(np.pi * np.hypot(2.0 / hy, 2.0 / hz))
+        wl = Workload(name, ne, lengths, dirichlet, cuts, 8.0 * ne[0], 1e-6, seed, density="crater", n_blobs=10,
+                      extra={"kmin": kmin, "kmax": kmax, "robin_kind": 2}, up=1)
     else:
         raise KeyError(name)
     for k, v in over.items():
@@ -138,4 +159,4 @@ def small(ne, nparts, p_times_h=8.0, bc=None, seed=0, tol=1e-10, density="blobs"
                     p_times_h / h, tol, seed, density=density, n_blobs=3)
 
 
-WORKLOADS = ("c1", "c2", "c3", "c4", "c5")
+WORKLOADS = ("c1", "c2", "c3", "c4", "c5", "c5copy", "slab32", "slab64", "slab128")

@@ -25,3 +25,21 @@ def test_candidate_copy_workload_matches_the_large_one_per_subdomain():
     # both have 16^3-element subdomains, so p h and q / h carry over
     assert [small.ne[a] // (len(small.cuts[a]) + 1) for a in range(3)] == [16, 16, 16]
     assert [large.ne[a] // (len(large.cuts[a]) + 1) for a in range(3)] == [16, 16, 16]
+
+
+def test_crater_field_vertical_axis_is_a_relabelling():
+    from synth.generators import crater_density
+    a = crater_density((6, 4, 5), (1.0, 0.3, 0.8), seed=2, up=1)   # y vertical
+    b = crater_density((6, 5, 4), (1.0, 0.8, 0.3), seed=2, up=2)   # z vertical, y and z swapped
+    assert np.allclose(a.reshape(5, 4, 6).transpose(1, 0, 2), b.reshape(4, 5, 6))
+
+
+def test_slab_workloads_have_the_paper_shape():
+    for parts in (32, 64, 128):
+        wl = workload(f"slab{parts}")
+        assert wl.nparts == (parts, 1, 1) and wl.tol == 1e-6 and wl.up == 1
+        widths = np.diff([0, *wl.cuts[0], wl.ne[0]])
+        assert widths.sum() == 320 and widths.max() - widths.min() <= 1
+        assert abs(wl.lengths[1] / wl.lengths[0] - 15.0 / 250.0) < 1e-12
+        assert wl.n_nodes == 641 * 39 * 641
+        assert wl.extra["kmin"] < wl.extra["kmax"]

@@ -289,8 +289,9 @@ std::vector<std::pair<int, int>> fused_candidates(const sos_ctx* c) {
   std::vector<std::pair<int, int>> out;
   for (int cpt = 1; cpt <= 4; ++cpt) {
     const int tmin = std::max(64, ((smax + cpt - 1) / cpt + 63) / 64 * 64);
-    for (int mul2 : {2, 3, 4, 6}) {
-      const int t = (tmin * mul2 / 2 + 63) / 64 * 64;
+    std::vector<int> sizes = {tmin, tmin + 64, tmin + 128};
+    for (int mul2 : {3, 4, 6}) sizes.push_back((tmin * mul2 / 2 + 63) / 64 * 64);
+    for (int t : sizes) {
       if (t > launch_bound(cpt) || fused_lds_need(c, t, cpt) > c->lds_limit) continue;
       if (std::find(out.begin(), out.end(), std::make_pair(t, cpt)) == out.end()) out.emplace_back(t, cpt);
     }

@@ -43,6 +43,24 @@ __device__ __forceinline__ T& at(T* base, uint32_t li) {
   return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + li * (uint32_t)sizeof(T));
 }
 
+// Data that another workgroup of the same launch writes or reads (the halo
+// planes of a team of workgroups sharing one subdomain, the team's partial
+// sums) goes through agent-scope relaxed atomic loads and stores: they are
+// coherent across the L2 caches of all XCDs by themselves, so the team barrier
+// needs no L2 write-back or invalidation (which would also evict every other
+// vector of the sweep). Ordering comes from waiting for all stores before the
+// barrier arrival and from issuing these loads after it.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt vmcnt(0): every vector memory operation of the wave has completed
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 
 // ---------------------------------------------------------------------------- 1D rows
 
@@ -293,7 +311,12 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     if constexpr (ZU) return sl.uz1;
     else return sl.z1[m];
   };
-  using Raw = decltype(fetch(uint32_t(0)));
+  using Raw = decltype(fetch(uint32_t(0), false));
+  // coh: the plane lies outside the block's own z-range (another block of a
+  // team writes it); edge: an own plane within two of the range's ends (the
+  // neighbouring team members read it)
+  auto coh_of = [&](int k) { return k < sl.uz0 || k >= sl.uz1; };
+  auto edge_of = [&](int k) { return k < sl.uz0 + 2 || k >= sl.uz1 - 2; };
   T acc[CPT][5];
   T pr[CPT][3];
   // prefetch ring: slot q holds the operands of the step that is congruent to
@@ -312,7 +335,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       // unconditional load from a clamped, always valid plane: a fixed number
       // of loads per step lets every use wait for its own load only
       const int kq = min(max(zlo(m) - 2 + q, 0), sl.nz - 1);
-      raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq));
+      raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
     }
   }
   const int steps = sl.seglen + 4;
@@ -332,12 +355,12 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       // subdomain, with own = false): its stores are off, its result unused
       const int kc = min(max(kp[m], 0), sl.nz - 1);
       const bool own = sl.act[m] && kp[m] >= zlo(m) && kp[m] < zhi(m);
-      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, slot_dinv(sl, m, kc));
+      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, edge_of(kc), slot_dinv(sl, m, kc));
       const T v = inr[m] ? T(op_of(mv)) : T(0);
       if (inr[m]) lds[sl.lp[m] + po] = v;
       pr[m][2] = inr[m] ? T(carry_of(mv)) : T(0);
       const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
-      raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq));
+      raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
     }
     __syncthreads();
 #pragma unroll
@@ -398,7 +421,8 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
         const int k = zlo(m) - 4 + step;
         const bool en = sl.act[m] && k >= zlo(m) && k < zhi(m);
         const int kc = min(max(k, 0), sl.nz - 1);
-        store(uint32_t(sl.c[m] + sl.S * kc), en, sl.i[m], sl.j[m], kc, acc[m][0], pr[m][0], slot_dinv(sl, m, kc));
+        store(uint32_t(sl.c[m] + sl.S * kc), en, edge_of(kc), sl.i[m], sl.j[m], kc, acc[m][0], pr[m][0],
+              slot_dinv(sl, m, kc));
       }
       acc[m][0] = acc[m][1];
       acc[m][1] = acc[m][2];
@@ -427,11 +451,15 @@ struct Pair {
 
 // Launch bound per x-y columns per thread (the host never launches more).
 template <int CPT>
+// Two columns per thread: up to 11 waves (3 per SIMD, 168 VGPRs); three: up to
+// 8 waves (2 per SIMD, 256 VGPRs). A block a few waves larger than the plane
+// needs spreads the second (third) column of the threads over more waves, so
+// no SIMD carries more of them than the others.
 struct Bound {
-  static constexpr int value = CPT == 2 ? 576 : (CPT == 3 ? 384 : 1024);
+  static constexpr int value = CPT == 2 ? 704 : (CPT == 3 ? 512 : 1024);
 };
 
-int launch_bound(int cpt) { return cpt == 2 ? 576 : (cpt == 3 ? 384 : 1024); }
+int launch_bound(int cpt) { return cpt == 2 ? 704 : (cpt == 3 ? 512 : 1024); }
 
 // Robin data added to the local right-hand side at node (i, j, k).
 struct LamOff {
@@ -534,9 +562,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   const double* __restrict__ ub = u + sl.off;
   const double* __restrict__ bb = b + sl.off;
   TO* __restrict__ rb = r + sl.off;
-  auto fetch = [=](uint32_t li) { return Pair<double>{at(ub, li), at(bb, li)}; };
-  auto make = [](const Pair<double>& v, uint32_t, bool, double) { return OpCarry<double>{v.a, v.b}; };
-  auto store = [&](uint32_t li, bool en, int, int, int, double q, double bv, double dinv) {
+  auto fetch = [=](uint32_t li, bool) { return Pair<double>{at(ub, li), at(bb, li)}; };
+  auto make = [](const Pair<double>& v, uint32_t, bool, bool, double) { return OpCarry<double>{v.a, v.b}; };
+  auto store = [&](uint32_t li, bool en, bool, int, int, int, double q, double bv, double dinv) {
     if (!en) return;
     const TO rt = TO(bv - q);
     at(rb, li) = rt;
@@ -571,9 +599,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, con
   const double* __restrict__ utb = ut + sl.off;
   const double* __restrict__ fb = f + sl.off;
   double* __restrict__ rhob = rho + sl.off;
-  auto fetch = [=](uint32_t li) { return at(utb, li); };
-  auto make = [](double v, uint32_t, bool, double) { return v; };
-  auto store = [=](uint32_t li, bool en, int, int, int, double q, double, double) {
+  auto fetch = [=](uint32_t li, bool) { return at(utb, li); };
+  auto make = [](double v, uint32_t, bool, bool, double) { return v; };
+  auto store = [=](uint32_t li, bool en, bool, int, int, int, double q, double, double) {
     if (en) at(rhob, li) = at(fb, li) - q;
   };
   zmarch(sl, lds, fetch, make, store);
@@ -593,9 +621,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockD
   __syncthreads();
   const T* __restrict__ xb = x + sl.off;
   T* __restrict__ yb = y + sl.off;
-  auto fetch = [=](uint32_t li) { return at(xb, li); };
-  auto make = [](T v, uint32_t, bool, T) { return v; };
-  auto store = [=](uint32_t li, bool en, int, int, int, T q, T, T) {
+  auto fetch = [=](uint32_t li, bool) { return at(xb, li); };
+  auto make = [](T v, uint32_t, bool, bool, T) { return v; };
+  auto store = [=](uint32_t li, bool en, bool, int, int, int, T q, T, T) {
     if (en) at(yb, li) = q;
   };
   zmarch(sl, lds, fetch, make, store);
@@ -723,13 +751,13 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const T* __restrict__ pob = pold + sl.off;
   T* __restrict__ pnb = pnew + sl.off;
   T* __restrict__ qb = q + sl.off;
-  auto fetch = [=](uint32_t li) { return Pair<T>{at(rb, li), at(pob, li)}; };
-  auto make = [=](Pair<T> v, uint32_t li, bool own, T dinv) {
+  auto fetch = [=](uint32_t li, bool) { return Pair<T>{at(rb, li), at(pob, li)}; };
+  auto make = [=](Pair<T> v, uint32_t li, bool own, bool, T dinv) {
     const T pn = dinv * v.a + (first ? T(0) : tb * v.b);
     if (own) at(pnb, li) = pn;
     return pn;
   };
-  auto store = [&](uint32_t li, bool en, int, int, int, T qv, T pk, T) {
+  auto store = [&](uint32_t li, bool en, bool, int, int, int, T qv, T pk, T) {
     if (!en) return;
     at(qb, li) = qv;
     a0 += double(pk) * double(qv);
@@ -803,9 +831,12 @@ struct Five {
 };
 
 // Sum the block partials of the T members of a team (the blocks that share
-// one subdomain): publish, agent-scope release on the team counter, bounded
-// spin with acquire, fixed-order sum. Every member gets the same sums. Epoch
-// e uses partial slots (e & 1); the counter reaches T (e + 1) after epoch e.
+// one subdomain): wait until every store of the block has completed, publish
+// the partials with coherent stores, increment the team counter, bounded spin,
+// coherent loads of the partials, fixed-order sum. Every member gets the same
+// sums. Epoch e uses partial slots (e & 1); the counter reaches T (e + 1)
+// after epoch e. The halo planes the next sweep reads from the other members
+// were written with coherent stores before their arrival (see ld_coh).
 constexpr long kSpinLimit = 1L << 26;
 
 template <int N>
@@ -813,15 +844,20 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
   if (a.team <= 1) return;
   __shared__ double tsum[N];
   __shared__ int tfail;
+  // every wave's stores of the sweep (the coherent ones among them) complete
+  // before the block arrives
+  wait_vm_all();
+  __syncthreads();
   if (threadIdx.x == 0) {
     double* slot = a.team_part + (((size_t)s * a.team + tau) * 2 + (epoch & 1)) * 4;
 #pragma unroll
-    for (int n = 0; n < N; ++n) slot[n] = v[n];
-    __hip_atomic_fetch_add(&a.team_cnt[s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    for (int n = 0; n < N; ++n) st_coh(&slot[n], v[n]);
+    wait_vm_all();
+    __hip_atomic_fetch_add(&a.team_cnt[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = (unsigned)a.team * (unsigned)(epoch + 1);
     long spins = 0;
     int f = 0;
-    while (__hip_atomic_load(&a.team_cnt[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&a.team_cnt[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++spins > kSpinLimit) {
         f = 1;
         break;
@@ -833,7 +869,7 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
     for (int m = 0; m < a.team; ++m) {
       const double* o = a.team_part + (((size_t)s * a.team + m) * 2 + (epoch & 1)) * 4;
 #pragma unroll
-      for (int n = 0; n < N; ++n) acc[n] += o[n];
+      for (int n = 0; n < N; ++n) acc[n] += ld_coh(&o[n]);
     }
 #pragma unroll
     for (int n = 0; n < N; ++n) tsum[n] = acc[n];
@@ -856,7 +892,11 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 // gamma = r'u, delta = w'u and r'r; then beta = gamma/gamma_old and
 // alpha = gamma / (delta - beta gamma / alpha_old). r, w, s, p are double
 // buffered (halo planes of one segment are read while another writes).
-template <typename T, int CPT, bool Q, bool ZU>
+// COH (a team of more than one block): every load and store of r, w, s, p
+// (the vectors whose halo planes the team members exchange) is coherent
+// (ld_coh / st_coh), so the team barrier needs no cache maintenance; a fixed
+// instruction form on every plane keeps the prefetch waits exact.
+template <typename T, int CPT, bool Q, bool ZU, bool COH>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
@@ -899,6 +939,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   int t = 0, brk = 0;
+  if (COH != (TM > 1)) brk = 1;  // the host pairs the coherent variant with teams
   if (!isfinite(rr)) brk = 1;
   if (ZU && sl.G != 1) brk = 1;  // the host selects ZU only when every block has one segment
   if (!brk && rr > stop2 && a.max_inner > 0) {
@@ -907,15 +948,16 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     {
       const T* __restrict__ r0 = r0b + sl.off;
       T* __restrict__ w0 = w0b + sl.off;
-      auto fetch = [=](uint32_t li) { return at(r0, li); };
-      auto make = [&](T rv, uint32_t, bool own, T dinv) {
+      auto fetch = [=](uint32_t li, bool) { return at(r0, li); };  // r0: written by an earlier launch
+      auto make = [&](T rv, uint32_t, bool own, bool, T dinv) {
         const T u = dinv * rv;
         if (own) g0 += double(rv) * double(u);
         return u;
       };
-      auto store = [&](uint32_t li, bool en, int, int, int, T wv, T uk, T) {
+      auto store = [&](uint32_t li, bool en, bool, int, int, int, T wv, T uk, T) {
         if (!en) return;
-        at(w0, li) = wv;
+        if constexpr (COH) st_coh(&at(w0, li), wv);
+        else at(w0, li) = wv;
         d0 += double(wv) * double(uk);
       };
       zmarch<ZU>(sl, lds, fetch, make, store);
@@ -942,16 +984,23 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       // per-thread partial sums in the inner precision (a few dozen terms),
       // combined across the block in FP64
       T ag = T(0), ad = T(0), ar = T(0);
-      auto fetch = [=](uint32_t li) {
+      auto fetch = [=](uint32_t li, bool) {
         Five<T> v;
-        v.r = at(rc, li);
-        v.w = at(wc, li);
-        v.s = at(sc, li);
-        v.p = at(pc, li);
-        v.x = at(xs, li);
+        if constexpr (COH) {
+          v.r = ld_coh(&at(rc, li));
+          v.w = ld_coh(&at(wc, li));
+          v.s = ld_coh(&at(sc, li));
+          v.p = ld_coh(&at(pc, li));
+        } else {
+          v.r = at(rc, li);
+          v.w = at(wc, li);
+          v.s = at(sc, li);
+          v.p = at(pc, li);
+        }
+        v.x = at(xs, li);  // x: own planes only, never exchanged
         return v;
       };
-      auto make = [&](const Five<T>& v, uint32_t li, bool own, T dinv) {
+      auto make = [&](const Five<T>& v, uint32_t li, bool own, bool, T dinv) {
         // the first iteration has no previous direction and no iterate (the
         // buffers may hold anything, so select rather than scale by zero)
         const T vp = first ? T(0) : v.p, vs = first ? T(0) : v.s, vx = first ? T(0) : v.x;
@@ -960,18 +1009,25 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         const T rn = v.r - ta * sn;
         const T un = dinv * rn;
         if (own) {
-          at(pn_, li) = pn;
-          at(sn_, li) = sn;
-          at(rn_, li) = rn;
+          if constexpr (COH) {
+            st_coh(&at(pn_, li), pn);
+            st_coh(&at(sn_, li), sn);
+            st_coh(&at(rn_, li), rn);
+          } else {
+            at(pn_, li) = pn;
+            at(sn_, li) = sn;
+            at(rn_, li) = rn;
+          }
           at(xs, li) = vx + ta * pn;
           ag += rn * un;
           ar += rn * rn;
         }
         return un;
       };
-      auto store = [&](uint32_t li, bool en, int, int, int, T wv, T uk, T) {
+      auto store = [&](uint32_t li, bool en, bool, int, int, int, T wv, T uk, T) {
         if (!en) return;
-        at(wn_, li) = wv;
+        if constexpr (COH) st_coh(&at(wn_, li), wv);
+        else at(wn_, li) = wv;
         ad += wv * uk;
       };
       zmarch<ZU>(sl, lds, fetch, make, store);
@@ -1466,7 +1522,7 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
                                    hipStream_t st) {
   const dim3 grid(d.geo.n_sub * a.team), block(threads);
   if (a.team <= 1) {
-    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU>), grid, block, lds, st, d, L.bfirst, a);
+    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, false>), grid, block, lds, st, d, L.bfirst, a);
     return hipGetLastError();
   }
   // team barriers spin: every block of the grid must be resident at once
@@ -1474,7 +1530,7 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
   const int32_t* bf = L.bfirst;
   FusedArgs aa = a;
   void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q, ZU>, grid, block, args, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q, ZU, true>, grid, block, args, (unsigned)lds, st);
 }
 
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,

@@ -48,7 +48,8 @@ def baseline_metric():
 def measured_traffic(launch_bytes, st):
     """HBM bytes per fused-kernel launch from committed rocprofv3 counters
     (FETCH_SIZE + WRITE_SIZE, each scaled by its reading for a plain copy),
-    if they were taken on the current kernel source with the same block shape;
+    if they were taken on the current kernel source with the same columns per
+    thread and team size;
     per launch of this run (the counters' ratio to the algorithmic bytes)."""
     try:
         pmc = json.load(open(PMC_FILE))
@@ -56,8 +57,7 @@ def measured_traffic(launch_bytes, st):
         return None
     if pmc.get("kernel_sha") != kernel_sha():
         return None
-    if (pmc.get("block"), pmc.get("cols_per_thread"), pmc.get("team")) != (st["block"], st["cols_per_thread"],
-                                                                           st["team"]):
+    if (pmc.get("cols_per_thread"), pmc.get("team")) != (st["cols_per_thread"], st["team"]):
         return None
     return pmc["traffic_over_algorithmic"] * launch_bytes
 

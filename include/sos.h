@@ -116,6 +116,16 @@ typedef struct {
   int32_t timing;      /* 1: time every fused-kernel launch with HIP events
                           (launches eagerly: events inside a graph are not
                           readable)                                           */
+  int32_t wave_rows;   /* with block != 0: 1 = each wave of the fused kernel
+                          owns whole x-rows of the plane (one workgroup
+                          barrier per plane; EINVAL if block/64 waves of
+                          64 x cols columns cannot cover every subdomain's
+                          plane that way); the autotuner tries both forms  */
+  int32_t resident;    /* 1 (default): the FP32 fused kernel may keep the CG
+                          direction p and the correction x in LDS for the
+                          whole launch where they fit (uniform z-ranges;
+                          with block != 0 it does, the autotuner tries both);
+                          0: never                                          */
 } sos_opts;
 
 typedef struct {
@@ -127,12 +137,18 @@ typedef struct {
   double kernel_ms;       /* timing = 1: summed duration of the fused CG kernel
                              (SOS_BATCHED) or of the CG step kernels (STEPWISE) */
   int64_t kernel_launches;/* number of launches summed in kernel_ms             */
-  double kernel_bytes;    /* algorithmic bytes of those launches (per CG
-                             iteration and local unknown: 10 words read/written
-                             + the per-solve setup and update)   */
+  double kernel_bytes;    /* algorithmic bytes of those launches: SOS_BATCHED
+                             12 words per CG iteration and local unknown (a
+                             PCG iteration with its dot products fused into the
+                             operator sweep) + per solve the read of x and the
+                             FP64 update of u; SOS_STEPWISE the 10 vectors its
+                             two kernels read and write per iteration          */
   int32_t block;          /* workgroup size used by the fused CG kernel         */
   int32_t cols_per_thread;/* x-y columns per thread of the fused CG kernel      */
   int32_t team;           /* blocks per subdomain of the fused CG kernel        */
+  int32_t wave_rows;      /* 1: each wave of the fused CG kernel owns whole
+                             x-rows of the plane (one barrier per plane)       */
+  int32_t resident;       /* 1: the fused CG kernel keeps p and x in LDS        */
 } sos_stats;
 
 /* Fill *opts with defaults for the given precision. */

@@ -88,8 +88,9 @@ struct sos_ctx {
   bool own_stream = false;
   // fused kernel launch shape
   int fused_threads = 0, fused_cpt = 1, fused_team = 1;
+  int fused_ra = 0;   // wave-owned rows in the fused kernel
+  int fused_res = 0;  // p and x resident in LDS when they fit (FP32, uniform z)
   size_t fused_lds = 0;
-  unsigned* team_cnt = nullptr;  // per-subdomain team barrier counters
   double* team_part = nullptr;   // team partial sums
   bool tuned = false;    // fused block shape chosen (explicit or autotuned)
   double tune_ms = 0.0;  // duration of the chosen shape in the tuning run
@@ -110,7 +111,6 @@ namespace {
 int64_t align64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
 constexpr int kStallOuter = 2000;  // outer iterations without 1% progress
-constexpr int kMaxTeam = 8;        // blocks per subdomain in the fused kernel
 constexpr int kMaxCopies = 4096;   // independent problem copies of one context
 
 void release(sos_ctx* c) {
@@ -120,7 +120,7 @@ void release(sos_ctx* c) {
   for (auto e : c->gevents) hipEventDestroy(e);
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
-                  c->part, c->part_norm, c->d_res, c->psi, c->team_cnt, c->team_part,
+                  c->part, c->part_norm, c->d_res, c->psi, c->team_part,
                   c->scal, c->ndone, c->counters};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -153,6 +153,9 @@ int check_opts(const sos_opts* o) {
   if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64))
     return fail(SOS_EINVAL, "opts.block must be 0 or a multiple of 64 in [64, 1024]");
   if (o->team < 0 || o->team > kMaxTeam) return fail(SOS_EINVAL, "opts.team must be in [0, %d]", kMaxTeam);
+  if (o->wave_rows != 0 && o->wave_rows != 1) return fail(SOS_EINVAL, "opts.wave_rows must be 0 or 1");
+  if (o->wave_rows && !o->block) return fail(SOS_EINVAL, "opts.wave_rows needs opts.block");
+  if (o->resident != 0 && o->resident != 1) return fail(SOS_EINVAL, "opts.resident must be 0 or 1");
   return SOS_OK;
 }
 
@@ -238,7 +241,7 @@ size_t fused_lds_need(const sos_ctx* c, int threads, int cpt) {
 
 // Sets the fused kernel's block shape; cpt = 0 picks the fewest columns per
 // thread that cover the largest x-y plane.
-int fused_shape(sos_ctx* c, int threads, int cpt = 0) {
+int fused_shape(sos_ctx* c, int threads, int cpt = 0, int ra = 0, int res = 0) {
   const int smax = smax_plane(c);
   if (threads == 0) {
     int k = 1;
@@ -255,8 +258,19 @@ int fused_shape(sos_ctx* c, int threads, int cpt = 0) {
                 launch_bound(cpt));
   const size_t lds = fused_lds_need(c, threads, cpt);
   if (lds > c->lds_limit) return fail(SOS_EINVAL, "fused kernel needs %zu bytes of LDS (limit %zu)", lds, c->lds_limit);
+  if (ra) {
+    if (threads % 64) return fail(SOS_EINVAL, "wave-owned rows need a multiple of 64 threads");
+    for (auto& s : c->subs) {
+      const int w = ra_waves(s.n[0], s.n[1], cpt);
+      if (w < 1 || w > threads / 64)
+        return fail(SOS_EINVAL, "wave-owned rows: %d waves of %d columns cannot cover a %dx%d plane", threads / 64,
+                    64 * cpt, s.n[0], s.n[1]);
+    }
+  }
   c->fused_threads = threads;
   c->fused_cpt = cpt;
+  c->fused_ra = ra ? 1 : 0;
+  c->fused_res = res ? 1 : 0;
   c->fused_lds = lds;
   return SOS_OK;
 }
@@ -264,6 +278,7 @@ int fused_shape(sos_ctx* c, int threads, int cpt = 0) {
 // True when every block of the fused kernel (every subdomain and team member)
 // marches a single segment, so the uniform-z kernel variant applies.
 bool fused_one_segment(const sos_ctx* c) {
+  if (c->fused_ra) return true;  // wave-owned rows: one segment by construction
   const int T = c->fused_team;
   for (auto& s : c->subs)
     for (int tau = 0; tau < T; ++tau) {
@@ -281,22 +296,55 @@ int set_team(sos_ctx* c, int team) {
   return SOS_OK;
 }
 
+struct Shape {
+  int threads, cpt, ra, res;
+  bool operator==(const Shape& o) const {
+    return threads == o.threads && cpt == o.cpt && ra == o.ra && res == o.res;
+  }
+};
+
 // Candidate block shapes of the fused kernel: for 1..4 columns per thread,
 // the smallest block covering the largest plane and 1.5x, 2x, 3x that size
-// (more segments per block on small planes), within the kernel bounds and LDS.
-std::vector<std::pair<int, int>> fused_candidates(const sos_ctx* c) {
+// (more segments per block on small planes), and the block of wave-owned rows,
+// within the kernel bounds and LDS.
+std::vector<Shape> fused_candidates(const sos_ctx* c) {
   const int smax = smax_plane(c);
-  std::vector<std::pair<int, int>> out;
+  std::vector<Shape> out;
+  auto add = [&](Shape sh) {
+    if (sh.threads > launch_bound(sh.cpt) || fused_lds_need(c, sh.threads, sh.cpt) > c->lds_limit) return;
+    if (std::find(out.begin(), out.end(), sh) == out.end()) out.push_back(sh);
+  };
   for (int cpt = 1; cpt <= 4; ++cpt) {
     const int tmin = std::max(64, ((smax + cpt - 1) / cpt + 63) / 64 * 64);
     std::vector<int> sizes = {tmin, tmin + 64, tmin + 128};
     for (int mul2 : {3, 4, 6}) sizes.push_back((tmin * mul2 / 2 + 63) / 64 * 64);
-    for (int t : sizes) {
-      if (t > launch_bound(cpt) || fused_lds_need(c, t, cpt) > c->lds_limit) continue;
-      if (std::find(out.begin(), out.end(), std::make_pair(t, cpt)) == out.end()) out.emplace_back(t, cpt);
+    for (int t : sizes) add({t, cpt, 0, 0});
+    int waves = 0;
+    for (auto& s : c->subs) {
+      const int w = ra_waves(s.n[0], s.n[1], cpt);
+      waves = w < 1 ? 1 << 20 : std::max(waves, w);
     }
+    if (waves <= 16) add({64 * waves, cpt, 1, 0});
+  }
+  // each shape again with p and x resident in LDS (used where they fit)
+  if (c->fp32 && c->opts.resident) {
+    const size_t n = out.size();
+    for (size_t i = 0; i < n; ++i) out.push_back({out[i].threads, out[i].cpt, out[i].ra, 1});
   }
   return out;
+}
+
+// LDS bytes of the resident p and x of the fused kernel: the largest z-range
+// of a team member times its plane, two FP32 values per node.
+size_t fused_res_bytes(const sos_ctx* c) {
+  size_t need = 0;
+  const int T = c->fused_team;
+  for (auto& s : c->subs)
+    for (int tau = 0; tau < T; ++tau) {
+      const size_t zlen = (size_t)(((tau + 1) * s.n[2]) / T - (tau * s.n[2]) / T);
+      need = std::max(need, 2 * zlen * (size_t)s.n[0] * (size_t)s.n[1] * sizeof(float));
+    }
+  return need;
 }
 
 std::string tune_key(const sos_ctx* c) {
@@ -322,7 +370,7 @@ std::string tune_cache_path() {
   return std::string(home ? home : "/tmp") + "/.cache/sos_autotune.jsonl";
 }
 
-bool tune_lookup(const std::string& key, int* threads, int* cpt, int* team) {
+bool tune_lookup(const std::string& key, int* threads, int* cpt, int* team, int* ra, int* res) {
   FILE* f = fopen(tune_cache_path().c_str(), "r");
   if (!f) return false;
   char line[512];
@@ -333,15 +381,22 @@ bool tune_lookup(const std::string& key, int* threads, int* cpt, int* team) {
     const char* t = strstr(line, "\"threads\": ");
     const char* k = strstr(line, "\"cpt\": ");
     const char* m = strstr(line, "\"team\": ");
+    const char* w = strstr(line, "\"rows\": ");
     if (t && k && m && sscanf(t + 11, "%d", threads) == 1 && sscanf(k + 7, "%d", cpt) == 1 &&
-        sscanf(m + 8, "%d", team) == 1)
+        sscanf(m + 8, "%d", team) == 1) {
       found = true;
+      *ra = 0;
+      *res = 0;
+      if (w) (void)sscanf(w + 8, "%d", ra);
+      const char* v = strstr(line, "\"resident\": ");
+      if (v) (void)sscanf(v + 12, "%d", res);
+    }
   }
   fclose(f);
   return found;
 }
 
-void tune_store(const std::string& key, int threads, int cpt, int team, double ms) {
+void tune_store(const std::string& key, int threads, int cpt, int team, int ra, int res, double ms) {
   std::string path = tune_cache_path();
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos) {
@@ -352,8 +407,10 @@ void tune_store(const std::string& key, int threads, int cpt, int team, double m
   }
   FILE* f = fopen(path.c_str(), "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"team\": %d, \"ms\": %.4f}\n", key.c_str(),
-          threads, cpt, team, ms);
+  fprintf(f,
+          "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"team\": %d, \"rows\": %d, \"resident\": %d, "
+          "\"ms\": %.4f}\n",
+          key.c_str(), threads, cpt, team, ra, res, ms);
   fclose(f);
 }
 
@@ -402,9 +459,18 @@ FusedArgs fused_args(sos_ctx* c) {
   a.scal = c->scal;
   a.iters_total = c->counters;
   a.team = c->fused_team;
-  a.team_cnt = c->team_cnt;
   a.team_part = c->team_part;
   a.zu = fused_one_segment(c) ? 1 : 0;
+  a.rows = c->fused_ra;
+  a.res = 0;
+  a.lds_bytes = (uint32_t)c->fused_lds;
+  if (c->fused_res && c->fp32 && a.zu) {
+    const size_t total = c->fused_lds + fused_res_bytes(c);
+    if (total <= c->lds_limit) {
+      a.res = 1;
+      a.lds_bytes = (uint32_t)total;
+    }
+  }
   return a;
 }
 
@@ -419,7 +485,7 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
   HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
   HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->b, c->r, c->part,
-                         c->fused_team > 1 ? c->team_cnt : nullptr, st));
+                         c->fused_team > 1 ? c->team_part : nullptr, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
@@ -583,6 +649,8 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
     stats->kernel_bytes = (double)c->h_counters[1];
     stats->block = c->fused_threads;
     stats->cols_per_thread = c->fused_cpt;
+    stats->wave_rows = c->fused_ra;
+    stats->resident = fused_args(c).res;
     stats->team = c->fused_team;
   }
   if (!std::isfinite(res)) return fail(SOS_EBREAKDOWN, "non-finite global residual");
@@ -610,11 +678,13 @@ int autotune(sos_ctx* c) {
   if (c->tuned) return SOS_OK;
   c->tuned = true;
   const std::string key = tune_key(c);
-  int th = 0, cp = 0, tm = 0;
-  if (tune_lookup(key, &th, &cp, &tm) && fused_shape(c, th, cp) == SOS_OK && set_team(c, tm) == SOS_OK) return SOS_OK;
+  int th = 0, cp = 0, tm = 0, ra = 0, res = 0;
+  if (tune_lookup(key, &th, &cp, &tm, &ra, &res) && fused_shape(c, th, cp, ra, res && c->opts.resident) == SOS_OK &&
+      set_team(c, tm) == SOS_OK)
+    return SOS_OK;
   // block shapes are tuned unless fixed by opts.block, team sizes unless fixed by opts.team
-  std::vector<std::pair<int, int>> shapes;
-  if (c->opts.block) shapes.emplace_back(c->fused_threads, c->fused_cpt);
+  std::vector<Shape> shapes;
+  if (c->opts.block) shapes.push_back({c->fused_threads, c->fused_cpt, c->fused_ra, c->fused_res});
   else shapes = fused_candidates(c);
   std::vector<int> teams;
   if (c->opts.team) teams.push_back(c->opts.team);
@@ -629,17 +699,18 @@ int autotune(sos_ctx* c) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double best = INFINITY;
-  int bt = c->fused_threads, bc = c->fused_cpt, bm = c->fused_team;
+  int bt = c->fused_threads, bc = c->fused_cpt, bm = c->fused_team, br = c->fused_ra, bs = c->fused_res;
   for (int team : teams)
     for (auto& cd : shapes) {
-      if (fused_shape(c, cd.first, cd.second) != SOS_OK || set_team(c, team) != SOS_OK) continue;
+      if (fused_shape(c, cd.threads, cd.cpt, cd.ra, cd.res) != SOS_OK || set_team(c, team) != SOS_OK) continue;
+      if (cd.res && !fused_args(c).res) continue;  // p and x do not fit in LDS with this team
       double ms_min = INFINITY;
       bool ok = true;
       for (int rep = 0; rep < 2 && ok; ++rep) {
         HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
         HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
         HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->b, c->r, c->part,
-                               team > 1 ? c->team_cnt : nullptr, st));
+                               team > 1 ? c->team_part : nullptr, st));
         HIPCHK(hipEventRecord(e0, st));
         if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
                             st) != hipSuccess) {
@@ -655,8 +726,10 @@ int autotune(sos_ctx* c) {
       }
       if (ok && ms_min < best) {
         best = ms_min;
-        bt = cd.first;
-        bc = cd.second;
+        bt = cd.threads;
+        bc = cd.cpt;
+        br = cd.ra;
+        bs = cd.res;
         bm = team;
       }
     }
@@ -664,12 +737,12 @@ int autotune(sos_ctx* c) {
   hipEventDestroy(e1);
   HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
   HIPCHK(hipStreamSynchronize(st));
-  int rc = fused_shape(c, bt, bc);
+  int rc = fused_shape(c, bt, bc, br, bs);
   if (!rc) rc = set_team(c, bm);
   if (rc) return rc;
   c->tune_ms = best;
   invalidate_graph(c);
-  tune_store(key, bt, bc, bm, best);
+  tune_store(key, bt, bc, bm, br, bs, best);
   return SOS_OK;
 }
 
@@ -714,6 +787,8 @@ int sos_opts_default(sos_opts* o, int32_t precision) {
   o->stream = nullptr;
   o->block = 0;
   o->timing = 0;
+  o->wave_rows = 0;
+  o->resident = 1;
   return SOS_OK;
 }
 
@@ -905,7 +980,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
     }
   }
   c->tuned = opts->block != 0 && opts->team != 0;
-  if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block)) || (rc = set_team(c, opts->team ? opts->team : 1))) {
+  if ((rc = build_seg(c)) || (rc = fused_shape(c, opts->block, 0, opts->wave_rows, opts->resident)) || (rc = set_team(c, opts->team ? opts->team : 1))) {
     release(c);
     return rc;
   }
@@ -933,7 +1008,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
       (rc = dalloc_v(&c->s1, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
       (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4 + (size_t)copies)) ||
       (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2)) ||
-      (rc = dalloc(&c->team_cnt, c->subs.size())) || (rc = dalloc(&c->team_part, c->subs.size() * kMaxTeam * 2 * 4))) {
+      (rc = dalloc(&c->team_part, c->subs.size() * kMaxTeam * 2 * 4))) {
     release(c);
     return rc;
   }
@@ -1004,15 +1079,16 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
   if (rc) return rc;
   if ((o->precision == SOS_FP32_INNER) != (c->fp32 != 0)) return fail(SOS_EINVAL, "precision is fixed at setup");
   if (o->stream && o->stream != c->stream) return fail(SOS_EINVAL, "the stream is fixed at setup");
-  const int old_block = c->opts.block, old_team = c->opts.team;
+  const int old_block = c->opts.block, old_team = c->opts.team, old_rows = c->opts.wave_rows,
+            old_res = c->opts.resident;
   const double old_tol = c->opts.inner_tol, old_abs = c->opts.inner_abs;
   void* st = c->opts.stream;
   c->opts = *o;
   c->opts.stream = st;
-  const bool retune = o->block != old_block || o->team != old_team || o->inner_tol != old_tol ||
-                      o->inner_abs != old_abs;
+  const bool retune = o->block != old_block || o->team != old_team || o->wave_rows != old_rows ||
+                      o->resident != old_res || o->inner_tol != old_tol || o->inner_abs != old_abs;
   if (retune) {
-    rc = fused_shape(c, o->block);
+    rc = fused_shape(c, o->block, 0, o->wave_rows, o->resident);
     if (!rc) rc = set_team(c, o->team ? o->team : 1);
     if (rc) return rc;
     c->tuned = o->block != 0 && o->team != 0;

@@ -29,6 +29,7 @@ struct Dev {
   int32_t hasq;             // some face has a second-order coefficient q > 0
 };
 
+constexpr int kMaxTeam = 8;  // blocks per subdomain in the fused kernel
 constexpr int kMinSeg = 8;  // shortest z-segment of a march (planes)
 
 // Number of z-segments a block of `threads` threads with `cpt` x-y columns per
@@ -39,6 +40,15 @@ __host__ __device__ inline int march_segments(int nx, int ny, int zlen, int thre
   int gz = (zlen + kMinSeg - 1) / kMinSeg;
   if (g > gz) g = gz;
   return g < 1 ? 1 : g;
+}
+// Wave-owned rows: wave w of a block owns the x-rows [w R, (w + 1) R) of the
+// plane, R = ra_rows(nx, cpt) = floor(64 cpt / nx), so the x-pass of the
+// operator reads only LDS values its own wave wrote and needs no workgroup
+// barrier. Waves needed: ceil(ny / R); 0 when a row does not fit one wave.
+__host__ __device__ inline int ra_rows(int nx, int cpt) { return (64 * cpt) / nx; }
+__host__ __device__ inline int ra_waves(int nx, int ny, int cpt) {
+  const int R = ra_rows(nx, cpt);
+  return R < 1 ? 0 : (ny + R - 1) / R;
 }
 // LDS planes per march segment: the operand (two, alternating by step) and the
 // two y-pass results, each zero-padded by kPad.
@@ -62,8 +72,10 @@ hipError_t launch_face_sum(const Dev& d, int max_shell, const double* f, const d
                            hipStream_t st);
 // r = b - A u (FP64 apply), stored as Tr; partials (r'D^-1 r if rz, else 0),
 // r'r, b'b per block.
+// team_part (optional): the fused kernel's team slots, n_sub * kMaxTeam * 8
+// doubles, cleared for the launch that follows.
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u,
-                           const double* b, void* r_out, double* part, unsigned* team_cnt, hipStream_t st);
+                           const double* b, void* r_out, double* part, double* team_part, hipStream_t st);
 // Per-subdomain CG scalars from the residual partials (stepwise path).
 hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel,
                           double tol_abs, CgScal* scal, int32_t* ndone, hipStream_t st);
@@ -90,10 +102,15 @@ struct FusedArgs {
   CgScal* scal;
   unsigned long long* iters_total;  // [0] CG iterations, [1] algorithmic bytes
   int32_t team;                     // blocks per subdomain (1: no inter-block sync)
-  unsigned* team_cnt;               // n_sub barrier counters (zeroed by the residual kernel)
-  double* team_part;                // n_sub * team * 2 * 4 partial sums
+  double* team_part;                // n_sub * team * 2 * 4 tagged partial sums (cleared by
+                                    // the residual kernel before each launch)
   int32_t zu;                       // every block marches one segment (uniform z variant)
+  int32_t rows;                     // wave-owned rows (see ra_rows): one barrier per plane
+  int32_t res;                      // p and x resident in LDS (FP32, uniform z only)
+  uint32_t lds_bytes;               // dynamic LDS of the launch (march planes + resident p, x)
 };
+// lds: the march planes; with a.res the launch takes a.lds_bytes (march planes
+// and the resident p and x of the largest z-range, at least lds).
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st);
 // Robin exchange over all interfaces (in place, both directions).

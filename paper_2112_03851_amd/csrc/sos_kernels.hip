@@ -136,6 +136,7 @@ struct Slots {
   int64_t off;
   int c[CPT], i[CPT], j[CPT], g[CPT], z0[CPT], z1[CPT], lp[CPT];
   int uz0, uz1;  // the block's z-range (the segment of every slot when G == 1)
+  bool ra;       // wave-owned rows (G == 1): the x-pass needs no barrier
   bool act[CPT];
   T kx0[CPT], mx0[CPT], kx2[CPT], mx2[CPT];
   T ky0[CPT], my0[CPT], ky2[CPT], my2[CPT];
@@ -149,7 +150,7 @@ struct Slots {
 
 template <typename T, int CPT, bool Q>
 __device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& d, const Geom& geo, int zb0,
-                                           int zb1, bool robin) {
+                                           int zb1, bool robin, bool ra = false) {
   sl.nx = d.n[0];
   sl.ny = d.n[1];
   sl.nz = d.n[2];
@@ -159,7 +160,11 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& 
   sl.off = d.off;
   const int NT = blockDim.x;
   const int zlen = zb1 - zb0;
-  sl.G = march_segments(sl.nx, sl.ny, zlen, NT, CPT);
+  // wave-owned rows: one segment, R rows per wave (the caller checks that the
+  // block's waves cover the plane)
+  sl.ra = ra;
+  sl.G = ra ? 1 : march_segments(sl.nx, sl.ny, zlen, NT, CPT);
+  const int R = ra ? ra_rows(sl.nx, CPT) : 0;
   sl.uz0 = zb0;
   sl.uz1 = zb1;
   sl.seglen = (zlen + sl.G - 1) / sl.G;
@@ -198,13 +203,27 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& 
   mz0[3] = T(4) * sl.zms;
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
-    const int sigma = threadIdx.x + NT * m;
-    const int g = sigma / sl.S;
-    const int col = sigma - g * sl.S;
+    int g, col;
+    bool cover;
+    if (ra) {
+      // slot q = lane + 64 m of wave w: row w R + q / nx, column q % nx; a
+      // slot past the wave's rows or the plane takes column 0 and stays idle
+      const int q = (threadIdx.x & 63) + 64 * m;
+      const int rq = q / sl.nx;
+      const int jr = (threadIdx.x >> 6) * R + rq;
+      cover = rq < R && jr < sl.ny;
+      g = 0;
+      col = cover ? (q - rq * sl.nx) + sl.nx * jr : 0;
+    } else {
+      const int sigma = threadIdx.x + NT * m;
+      g = sigma / sl.S;
+      col = sigma - g * sl.S;
+      cover = g < sl.G;
+    }
     sl.g[m] = g;
     sl.z0[m] = zb0 + g * sl.seglen;
     sl.z1[m] = min(zb1, sl.z0[m] + sl.seglen);
-    sl.act[m] = (g < sl.G) && (sl.z0[m] < zb1);
+    sl.act[m] = cover && (sl.z0[m] < zb1);
     sl.c[m] = col;
     const int i = col % sl.nx, j = col / sl.nx;
     sl.i[m] = i;
@@ -316,7 +335,28 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
   // team writes it); edge: an own plane within two of the range's ends (the
   // neighbouring team members read it)
   auto coh_of = [&](int k) { return k < sl.uz0 || k >= sl.uz1; };
+  // inverse diagonal at plane k; with uniform z the row kind is uniform and a
+  // select chain on a scalar condition replaces the 0/1 blend
+  auto dinv_of = [&](int m, int k) {
+    if constexpr (ZU) {
+      const int c = k + sl.zklo;
+      const T d0 = sl.dv0[m], d1 = sl.dv1[m], d2 = sl.dv2[m], d3 = sl.dv3[m];
+      T dv = (c & 1) != 0 ? d0 : d1;
+      dv = c == 0 ? d2 : dv;
+      dv = c == sl.zne2 ? d3 : dv;
+      return dv;
+    } else {
+      return slot_dinv(sl, m, k);
+    }
+  };
   auto edge_of = [&](int k) { return k < sl.uz0 + 2 || k >= sl.uz1 - 2; };
+  // first operand plane of the march: two below the segment, or (uniform z)
+  // the subdomain's first plane when the segment starts there, since planes
+  // outside the subdomain contribute nothing
+  auto kfirst = [&](int m) {
+    if constexpr (ZU) return max(sl.uz0 - 2, 0);
+    else return sl.z0[m] - 2;
+  };
   T acc[CPT][5];
   T pr[CPT][3];
   // prefetch ring: slot q holds the operands of the step that is congruent to
@@ -334,11 +374,12 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     for (int q = 0; q < kPrefetch; ++q) {
       // unconditional load from a clamped, always valid plane: a fixed number
       // of loads per step lets every use wait for its own load only
-      const int kq = min(max(zlo(m) - 2 + q, 0), sl.nz - 1);
+      const int kq = min(max(kfirst(m) + q, 0), sl.nz - 1);
       raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
     }
   }
-  const int steps = sl.seglen + 4;
+  // the output of plane k is complete two steps after operand plane k + 2
+  const int steps = ZU ? sl.uz1 + 2 - kfirst(0) : sl.seglen + 4;
   const int PX = sl.PX, SP = sl.SP;
   auto one_step = [&](auto ucst, int step) {
     constexpr int U = decltype(ucst)::value;
@@ -349,20 +390,23 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     int kp[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-      kp[m] = zlo(m) - 2 + step;
+      kp[m] = kfirst(m) + step;
       inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] < sl.nz;
       // make() runs on every step (on a clamped, valid plane outside the
       // subdomain, with own = false): its stores are off, its result unused
       const int kc = min(max(kp[m], 0), sl.nz - 1);
       const bool own = sl.act[m] && kp[m] >= zlo(m) && kp[m] < zhi(m);
-      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, edge_of(kc), slot_dinv(sl, m, kc));
-      const T v = inr[m] ? T(op_of(mv)) : T(0);
-      if (inr[m]) lds[sl.lp[m] + po] = v;
-      pr[m][2] = inr[m] ? T(carry_of(mv)) : T(0);
+      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, edge_of(kc), dinv_of(m, kc));
+      if (inr[m]) lds[sl.lp[m] + po] = T(op_of(mv));
+      // a plane outside the subdomain is never stored, so its carry is unused
+      pr[m][2] = T(carry_of(mv));
       const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
       raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
     }
-    __syncthreads();
+    // uniform z: the steps past the subdomain's last plane only drain the
+    // accumulator ring and touch no LDS, so they skip both barriers
+    const bool sync = !ZU || kfirst(0) + step < sl.nz;
+    if (sync) __syncthreads();
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (inr[m]) {
@@ -376,7 +420,10 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
         lds[sl.lp[m] + 2 * SP] = v;
       }
     }
-    __syncthreads();
+    // wave-owned rows: the x-pass reads the y-pass results of its own wave
+    // (LDS operations of a wave complete in order), and the next step's y-pass
+    // rewrites them only after this wave's x-pass
+    if (sync && !sl.ra) __syncthreads();
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (inr[m]) {
@@ -386,7 +433,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
         const T v0 = V[0], v1 = V[-1] + V[1], v2 = V[-2] + V[2];
         T Sx = sl.kx0[m] * u0 + sl.kx1 * u1 + sl.kx2[m] * u2 + sl.mx0[m] * v0 + sl.mx1 * v1 + sl.mx2[m] * v2;
         T Tx = sl.mx0[m] * u0 + sl.mx1 * u1 + sl.mx2[m] * u2;
-        T zc = T(0);
+        T zc = T(0);  // second-order z-face term of the centre row
         if constexpr (Q) if (sl.hasq) {
           // second-order faces q (tangential stiffness with plain 1D factors):
           // an x-face adds q (Ky (x) Mz + My (x) Kz) on its plane, a y-face
@@ -410,25 +457,27 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
         const T c2 = rz.m2 * Sx + rz.k2 * Tx;
         acc[m][0] += c2;
         acc[m][1] += c1;
-        acc[m][2] += rz.m0 * Sx + rz.k0 * Tx + zc;
+        if constexpr (Q) acc[m][2] += rz.m0 * Sx + rz.k0 * Tx + zc;
+        else acc[m][2] += rz.m0 * Sx + rz.k0 * Tx;
         acc[m][3] += c1;
-        acc[m][4] += c2;
+        acc[m][4] = c2;
+      } else {
+        acc[m][4] = T(0);
       }
     }
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       {
-        const int k = zlo(m) - 4 + step;
+        const int k = kp[m] - 2;
         const bool en = sl.act[m] && k >= zlo(m) && k < zhi(m);
         const int kc = min(max(k, 0), sl.nz - 1);
         store(uint32_t(sl.c[m] + sl.S * kc), en, edge_of(kc), sl.i[m], sl.j[m], kc, acc[m][0], pr[m][0],
-              slot_dinv(sl, m, kc));
+              dinv_of(m, kc));
       }
       acc[m][0] = acc[m][1];
       acc[m][1] = acc[m][2];
       acc[m][2] = acc[m][3];
       acc[m][3] = acc[m][4];
-      acc[m][4] = T(0);
       pr[m][0] = pr[m][1];
       pr[m][1] = pr[m][2];
     }
@@ -495,13 +544,15 @@ __device__ __forceinline__ unsigned long long cg_bytes(const SubDesc& sd, int t,
   return n * ((unsigned long long)(10 * t - 2) * es + es + 16ull);
 }
 
-// Algorithmic bytes of a fused inner solve of t >= 1 iterations: the first
-// sweep reads r and writes w, iteration 0 reads r, w and writes r, w, s, p, x,
-// every later iteration reads and writes r, w, s, p, x; then u += x.
+// Algorithmic bytes of a fused inner solve of t >= 1 iterations: a
+// preconditioned CG iteration with its dot products fused into the operator
+// sweep moves 12 words per unknown (apply: read p, write q; updates of x, r, p
+// and z = D^-1 r: 7; dots: 3), whatever the kernel keeps on chip; then
+// u += x reads x and reads and writes u in FP64.
 __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int t, int es) {
   if (t <= 0) return 0ull;
   const unsigned long long n = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
-  return n * ((unsigned long long)(10 * t - 1) * es + es + 16ull);
+  return n * ((unsigned long long)(12 * t) * es + es + 16ull);
 }
 
 // ---------------------------------------------------------------------------- outer kernels
@@ -546,12 +597,13 @@ __global__ void k_face_sum(Dev d, const double* __restrict__ f, const double* __
 template <typename TO, int CPT, bool Q, bool RZ>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
                                                    const double* __restrict__ b, TO* __restrict__ r,
-                                                   double* __restrict__ part, unsigned* __restrict__ team_cnt) {
+                                                   double* __restrict__ part, double* __restrict__ team_part) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* lds = reinterpret_cast<double*>(smem);
-  // the fused kernel that follows counts its team barriers from zero
-  if (team_cnt && blockIdx.x == 0)
-    for (int i = threadIdx.x; i < d.geo.n_sub; i += blockDim.x) team_cnt[i] = 0u;
+  // the fused kernel that follows tags its team partials from epoch 0: clear
+  // every slot (tag 0)
+  if (team_part && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < d.geo.n_sub * kMaxTeam * 2 * 4; i += blockDim.x) team_part[i] = 0.0;
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
   Slots<double, CPT, Q> sl;
@@ -829,57 +881,77 @@ template <typename T>
 struct Five {
   T r, w, s, p, x;
 };
+template <typename T>
+struct Three {
+  T r, w, s;
+};
 
 // Sum the block partials of the T members of a team (the blocks that share
-// one subdomain): wait until every store of the block has completed, publish
-// the partials with coherent stores, increment the team counter, bounded spin,
-// coherent loads of the partials, fixed-order sum. Every member gets the same
-// sums. Epoch e uses partial slots (e & 1); the counter reaches T (e + 1)
-// after epoch e. The halo planes the next sweep reads from the other members
-// were written with coherent stores before their arrival (see ld_coh).
+// one subdomain). Every store of the block's sweep completes first (the halo
+// planes the other members read next were written with coherent stores);
+// then the block publishes its partials with coherent stores, each carrying
+// the epoch in its eight lowest mantissa bits, and lanes of the first wave
+// spin (bounded) on the T members' slots until every tag reads the epoch:
+// arrival and data in one round trip. The tag costs at most 2^-44 of a
+// partial's value; the tagged bits are cleared and the partials summed in
+// member order, so every member gets the same sums. Epoch e uses slots
+// (e & 1) with tag (e + 1) mod 256; the slots are zeroed (tag 0) before each
+// launch, and a slot's previous tag is that of epoch e - 2, never equal.
 constexpr long kSpinLimit = 1L << 26;
+constexpr int kTeamSlot = 4;  // doubles per (member, parity) slot
+
+__device__ __forceinline__ double with_tag(double v, unsigned tag) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return __longlong_as_double((long long)((b & ~0xFFull) | tag));
+}
+__device__ __forceinline__ unsigned tag_of(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) & 0xFFull);
+}
 
 template <int N>
 __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int s, int tau, int epoch, int& fail) {
+  static_assert(N <= kTeamSlot, "partials per slot");
   if (a.team <= 1) return;
-  __shared__ double tsum[N];
-  __shared__ int tfail;
-  // every wave's stores of the sweep (the coherent ones among them) complete
-  // before the block arrives
+  __shared__ double tval[kMaxTeam * N];
+  __shared__ int tfl[kMaxTeam * N];
+  const unsigned tag = (unsigned)((epoch + 1) & 0xFF);
+  double* const base = a.team_part + (size_t)s * a.team * 2 * kTeamSlot;
   wait_vm_all();
   __syncthreads();
   if (threadIdx.x == 0) {
-    double* slot = a.team_part + (((size_t)s * a.team + tau) * 2 + (epoch & 1)) * 4;
+    double* slot = base + ((size_t)tau * 2 + (epoch & 1)) * kTeamSlot;
 #pragma unroll
-    for (int n = 0; n < N; ++n) st_coh(&slot[n], v[n]);
-    wait_vm_all();
-    __hip_atomic_fetch_add(&a.team_cnt[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned target = (unsigned)a.team * (unsigned)(epoch + 1);
+    for (int n = 0; n < N; ++n) st_coh(&slot[n], with_tag(v[n], tag));
+  }
+  if (threadIdx.x < a.team * N) {
+    const int m = threadIdx.x / N, n = threadIdx.x - m * N;
+    const double* q = base + ((size_t)m * 2 + (epoch & 1)) * kTeamSlot + n;
+    double val = ld_coh(q);
     long spins = 0;
     int f = 0;
-    while (__hip_atomic_load(&a.team_cnt[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (tag_of(val) != tag) {
       if (++spins > kSpinLimit) {
         f = 1;
         break;
       }
+      val = ld_coh(q);
     }
-    double acc[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) acc[n] = 0.0;
-    for (int m = 0; m < a.team; ++m) {
-      const double* o = a.team_part + (((size_t)s * a.team + m) * 2 + (epoch & 1)) * 4;
-#pragma unroll
-      for (int n = 0; n < N; ++n) acc[n] += ld_coh(&o[n]);
-    }
-#pragma unroll
-    for (int n = 0; n < N; ++n) tsum[n] = acc[n];
-    tfail = f;
+    tval[threadIdx.x] = with_tag(val, 0u);
+    tfl[threadIdx.x] = f;
   }
   __syncthreads();
+  int f = 0;
 #pragma unroll
-  for (int n = 0; n < N; ++n) v[n] = tsum[n];
-  fail |= tfail;
-  __syncthreads();
+  for (int n = 0; n < N; ++n) {
+    double acc = 0.0;
+    for (int m = 0; m < a.team; ++m) {
+      acc += tval[m * N + n];
+      f |= tfl[m * N + n];
+    }
+    v[n] = acc;
+  }
+  fail |= f;
+  // tval is rewritten only after the next sweep's barriers
 }
 
 // One block per subdomain (team = 1), or a team of blocks each owning a
@@ -892,11 +964,15 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 // gamma = r'u, delta = w'u and r'r; then beta = gamma/gamma_old and
 // alpha = gamma / (delta - beta gamma / alpha_old). r, w, s, p are double
 // buffered (halo planes of one segment are read while another writes).
-// COH (a team of more than one block): every load and store of r, w, s, p
-// (the vectors whose halo planes the team members exchange) is coherent
-// (ld_coh / st_coh), so the team barrier needs no cache maintenance; a fixed
-// instruction form on every plane keeps the prefetch waits exact.
-template <typename T, int CPT, bool Q, bool ZU, bool COH>
+// COH (a team of more than one block): every load and store of the vectors
+// whose halo planes the team members read is coherent (ld_coh / st_coh), so
+// the team barrier needs no cache maintenance; a fixed instruction form on
+// every plane keeps the prefetch waits exact.
+// RES: p and x stay in LDS for the whole launch (uniform z only). A halo plane
+// only needs u = D^-1 (r - alpha (w + beta s)), so p and x are read and
+// written by the thread that owns the node and never by another block; global
+// traffic per CG iteration drops from ten words per node to six.
+template <typename T, int CPT, bool Q, bool ZU, bool COH, bool RES>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
@@ -916,7 +992,8 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   const SubDesc sd = d.subs[s];
   const int zb0 = (tau * sd.n[2]) / TM, zb1 = ((tau + 1) * sd.n[2]) / TM;
   Slots<T, CPT, Q> sl;
-  slots_init(sl, sd, d.geo, zb0, zb1, true);
+  const bool ra = a.rows != 0;
+  slots_init(sl, sd, d.geo, zb0, zb1, true, ra);
   int epoch = 0, tfail = 0;
   // buffers chosen with selects, never through an indexed array: pointers
   // read back from a private array lose their global address space and the
@@ -938,10 +1015,19 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   const double stop2 = fmax(a.tol_rel * a.tol_rel * rr, a.tol_abs * a.tol_abs * bb);
   lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
+  // resident p and x: one LDS value per own node, index li - S uz0
+  T* const pres = lds + sl.G * kPlanes * sl.SP;
+  T* const xres = pres + (size_t)(zb1 - zb0) * sl.S;
+  const uint32_t plane0 = (uint32_t)(sl.S * zb0);
   int t = 0, brk = 0;
+  if (RES && (!ZU || (size_t)(sl.G * kPlanes * sl.SP + 2 * (zb1 - zb0) * sl.S) * sizeof(T) > a.lds_bytes))
+    brk = 1;  // the host sizes the LDS for the largest z-range
   if (COH != (TM > 1)) brk = 1;  // the host pairs the coherent variant with teams
   if (!isfinite(rr)) brk = 1;
   if (ZU && sl.G != 1) brk = 1;  // the host selects ZU only when every block has one segment
+  // wave-owned rows only where the block's waves cover the plane (host checked)
+  if (ra && (!ZU || ra_waves(sd.n[0], sd.n[1], CPT) < 1 || ra_waves(sd.n[0], sd.n[1], CPT) > (int)(blockDim.x >> 6)))
+    brk = 1;
   if (!brk && rr > stop2 && a.max_inner > 0) {
     // u0 = D^-1 r0, w0 = A u0, gamma0 = r0'u0, delta0 = w0'u0
     double g0 = 0.0, d0 = 0.0;
@@ -985,6 +1071,19 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       // combined across the block in FP64
       T ag = T(0), ad = T(0), ar = T(0);
       auto fetch = [=](uint32_t li, bool) {
+        if constexpr (RES) {
+          Three<T> v;
+          if constexpr (COH) {
+            v.r = ld_coh(&at(rc, li));
+            v.w = ld_coh(&at(wc, li));
+            v.s = ld_coh(&at(sc, li));
+          } else {
+            v.r = at(rc, li);
+            v.w = at(wc, li);
+            v.s = at(sc, li);
+          }
+          return v;
+        } else {
         Five<T> v;
         if constexpr (COH) {
           v.r = ld_coh(&at(rc, li));
@@ -999,15 +1098,36 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         }
         v.x = at(xs, li);  // x: own planes only, never exchanged
         return v;
+        }
       };
-      auto make = [&](const Five<T>& v, uint32_t li, bool own, bool, T dinv) {
+      auto make = [&](const auto& v, uint32_t li, bool own, bool, T dinv) {
         // the first iteration has no previous direction and no iterate (the
         // buffers may hold anything, so select rather than scale by zero)
-        const T vp = first ? T(0) : v.p, vs = first ? T(0) : v.s, vx = first ? T(0) : v.x;
-        const T pn = dinv * v.r + tb * vp;
+        const T vs = first ? T(0) : v.s;
         const T sn = v.w + tb * vs;
         const T rn = v.r - ta * sn;
         const T un = dinv * rn;
+        if constexpr (RES) {
+          if (own) {
+            const uint32_t q = li - plane0;
+            const T pn = fma(tb, first ? T(0) : pres[q], dinv * v.r);
+            pres[q] = pn;
+            xres[q] = fma(ta, pn, first ? T(0) : xres[q]);
+            if constexpr (COH) {
+              st_coh(&at(sn_, li), sn);
+              st_coh(&at(rn_, li), rn);
+            } else {
+              at(sn_, li) = sn;
+              at(rn_, li) = rn;
+            }
+            ag += rn * un;
+            ar += rn * rn;
+          }
+          return un;
+        } else {
+        // the same rounding as the resident form: explicit fused multiply-adds
+        const T vp = first ? T(0) : v.p, vx = first ? T(0) : v.x;
+        const T pn = fma(tb, vp, dinv * v.r);
         if (own) {
           if constexpr (COH) {
             st_coh(&at(pn_, li), pn);
@@ -1018,11 +1138,12 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
             at(sn_, li) = sn;
             at(rn_, li) = rn;
           }
-          at(xs, li) = vx + ta * pn;
+          at(xs, li) = fma(ta, pn, vx);
           ag += rn * un;
           ar += rn * rn;
         }
         return un;
+        }
       };
       auto store = [&](uint32_t li, bool en, bool, int, int, int, T wv, T uk, T) {
         if (!en) return;
@@ -1064,8 +1185,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (k + u < sl.z1[m]) {
-            xv[u] = at(xb, sl.c[m] + sl.S * (k + u));
-            uv[u] = at(ub, sl.c[m] + sl.S * (k + u));
+            const uint32_t li = sl.c[m] + sl.S * (k + u);
+            xv[u] = RES ? xres[li - plane0] : at(xb, li);
+            uv[u] = at(ub, li);
           }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -1443,20 +1565,20 @@ hipError_t launch_face_sum(const Dev& d, int max_shell, const double* f, const d
 }
 
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u, const double* b,
-                           void* r_out, double* part, unsigned* team_cnt, hipStream_t st) {
+                           void* r_out, double* part, double* team_part, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
   if (fp32 && rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_cnt));
+                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_part));
   } else if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_cnt));
+                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_part));
   } else if (rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_cnt));
+                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_part));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_cnt));
+                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_part));
   }
   });
   return hipGetLastError();
@@ -1517,12 +1639,12 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
   return hipGetLastError();
 }
 
-template <typename T, int C, bool Q, bool ZU>
+template <typename T, int C, bool Q, bool ZU, bool RES = false>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
                                    hipStream_t st) {
   const dim3 grid(d.geo.n_sub * a.team), block(threads);
   if (a.team <= 1) {
-    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, false>), grid, block, lds, st, d, L.bfirst, a);
+    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, false, RES>), grid, block, lds, st, d, L.bfirst, a);
     return hipGetLastError();
   }
   // team barriers spin: every block of the grid must be resident at once
@@ -1530,13 +1652,17 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
   const int32_t* bf = L.bfirst;
   FusedArgs aa = a;
   void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q, ZU, true>, grid, block, args, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q, ZU, true, RES>, grid, block, args,
+                                    (unsigned)lds, st);
 }
 
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st) {
+  if (a.res && (!fp32 || !a.zu || lds > a.lds_bytes)) return hipErrorInvalidValue;
   SOS_DISPATCH_Q(d.hasq, {
-    if (fp32 && a.zu) {
+    if (fp32 && a.zu && a.res) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, true>(d, L, threads, a.lds_bytes, a, st)));
+    } else if (fp32 && a.zu) {
       SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true>(d, L, threads, lds, a, st)));
     } else if (fp32) {
       SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, false>(d, L, threads, lds, a, st)));

@@ -49,14 +49,16 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("max_outer", C.c_int32),
                 ("max_inner", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_tol", C.c_double), ("inner_abs", C.c_double), ("G", C.c_double),
-                ("stream", C.c_void_p), ("block", C.c_int32), ("team", C.c_int32), ("timing", C.c_int32)]
+                ("stream", C.c_void_p), ("block", C.c_int32), ("team", C.c_int32), ("timing", C.c_int32),
+                ("wave_rows", C.c_int32), ("resident", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("checks", C.c_int32), ("inner_iters", C.c_int64),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("kernel_ms", C.c_double),
                 ("kernel_launches", C.c_int64), ("kernel_bytes", C.c_double), ("block", C.c_int32),
-                ("cols_per_thread", C.c_int32), ("team", C.c_int32)]
+                ("cols_per_thread", C.c_int32), ("team", C.c_int32), ("wave_rows", C.c_int32),
+                ("resident", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

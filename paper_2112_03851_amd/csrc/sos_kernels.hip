@@ -897,7 +897,9 @@ struct Three {
 // member order, so every member gets the same sums. Epoch e uses slots
 // (e & 1) with tag (e + 1) mod 256; the slots are zeroed (tag 0) before each
 // launch, and a slot's previous tag is that of epoch e - 2, never equal.
-constexpr long kSpinLimit = 1L << 26;
+// A member that waits longer than this (wall clock ticks, 100 MHz: about 1.3 s)
+// for the others gives up and reports a failed barrier (breakdown).
+constexpr unsigned long long kSpinTicks = 1ull << 27;
 constexpr int kTeamSlot = 4;  // doubles per (member, parity) slot
 
 __device__ __forceinline__ double with_tag(double v, unsigned tag) {
@@ -927,10 +929,10 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
     const int m = threadIdx.x / N, n = threadIdx.x - m * N;
     const double* q = base + ((size_t)m * 2 + (epoch & 1)) * kTeamSlot + n;
     double val = ld_coh(q);
-    long spins = 0;
+    const unsigned long long t0 = wall_clock64();
     int f = 0;
     while (tag_of(val) != tag) {
-      if (++spins > kSpinLimit) {
+      if (wall_clock64() - t0 > kSpinTicks) {
         f = 1;
         break;
       }
@@ -1639,6 +1641,16 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
   return hipGetLastError();
 }
 
+// True when the device's compute units can hold all `blocks` blocks of the
+// kernel at once (occupancy of the kernel alone, dynamic LDS included).
+static bool team_grid_resident(const void* fn, int threads, size_t lds, int blocks) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return false;
+  return (long long)per_cu * cus >= blocks;
+}
+
 template <typename T, int C, bool Q, bool ZU, bool RES = false>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
                                    hipStream_t st) {
@@ -1647,13 +1659,21 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
     hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, false, RES>), grid, block, lds, st, d, L.bfirst, a);
     return hipGetLastError();
   }
-  // team barriers spin: every block of the grid must be resident at once
+  // team barriers spin: every block of the grid must be resident at once.
+  // When the occupancy of the kernel alone admits the whole grid, a plain
+  // launch dispatches every block at once (and can be captured in a graph);
+  // otherwise the cooperative launch checks residency and fails instead. A
+  // member that still waits too long reports a failed barrier.
+  const void* fn = (const void*)k_fused_cg<T, C, Q, ZU, true, RES>;
+  if (team_grid_resident(fn, threads, lds, (int)grid.x)) {
+    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, true, RES>), grid, block, lds, st, d, L.bfirst, a);
+    return hipGetLastError();
+  }
   Dev dd = d;
   const int32_t* bf = L.bfirst;
   FusedArgs aa = a;
   void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel((const void*)k_fused_cg<T, C, Q, ZU, true, RES>, grid, block, args,
-                                    (unsigned)lds, st);
+  return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)lds, st);
 }
 
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,

@@ -64,7 +64,7 @@ struct sos_ctx {
   Dev dev{};
   SubDesc* d_subs = nullptr;
   FaceDesc* d_faces = nullptr;
-  int32_t* d_pairs = nullptr;
+  ExPair* d_expairs = nullptr;  // the pairs resolved for the exchange kernel
   int32_t* d_order = nullptr;
   Seg seg;
   // workspaces
@@ -118,7 +118,7 @@ void release(sos_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
   for (auto e : c->gevents) hipEventDestroy(e);
-  void* ptrs[] = {c->d_subs, c->d_faces, c->d_pairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
+  void* ptrs[] = {c->d_subs, c->d_faces, c->d_expairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_part,
                   c->scal, c->ndone, c->counters};
@@ -205,6 +205,7 @@ int build_seg(sos_ctx* c) {
   g.blocks.clear();
   g.bfirst.assign(1, 0);
   size_t lds64 = 0, lds32 = 0;
+  bool zu = true;
   for (int s = 0; s < n_sub; ++s) {
     const SubDesc& d = c->subs[s];
     const int nz = d.n[2];
@@ -213,6 +214,7 @@ int build_seg(sos_ctx* c) {
     for (int z = 0; z < nz; z += len) {
       BlockDesc b{s, z, std::min(nz, z + len), 0};
       g.blocks.push_back(b);
+      zu = zu && march_segments(d.n[0], d.n[1], b.z1 - b.z0, threads, cpt) == 1;
       lds64 = std::max(lds64, march_lds_bytes(d.n[0], d.n[1], b.z1 - b.z0, threads, cpt, 8));
       lds32 = std::max(lds32, march_lds_bytes(d.n[0], d.n[1], b.z1 - b.z0, threads, cpt, 4));
     }
@@ -224,6 +226,7 @@ int build_seg(sos_ctx* c) {
   g.L.cpt = cpt;
   g.L.lds64 = lds64;
   g.L.lds32 = lds32;
+  g.L.zu = zu ? 1 : 0;
   return SOS_OK;
 }
 
@@ -428,6 +431,46 @@ int dalloc_v(void** p, size_t bytes) {
   return SOS_OK;
 }
 
+// The exchange kernel's pair descriptors from the host face and subdomain
+// descriptors (again after every change of the Robin coefficients).
+hipError_t upload_expairs(sos_ctx* c) {
+  std::vector<ExPair> v;
+  v.reserve(c->pairs.size());
+  for (int32_t fi : c->pairs) {
+    const FaceDesc& F = c->faces[fi];
+    const FaceDesc& G = c->faces[F.opp];
+    ExPair P{};
+    const int ax = F.axis, ta = ax == 0 ? 1 : 0, tb = ax == 2 ? 1 : 2;
+    auto place = [&](const FaceDesc& X, int64_t* base, int64_t* sa, int64_t* sb) {
+      const SubDesc& sd = c->subs[X.s];
+      const int64_t st[3] = {1, sd.n[0], (int64_t)sd.n[0] * sd.n[1]};
+      *sa = st[ta];
+      *sb = st[tb];
+      *base = sd.off + (int64_t)(X.side ? sd.n[ax] - 1 : 0) * st[ax];
+    };
+    place(F, &P.base_s, &P.sa_s, &P.sb_s);
+    place(G, &P.base_j, &P.sa_j, &P.sb_j);
+    const SubDesc& sd = c->subs[F.s];
+    P.lam_f = F.lam_off;
+    P.lam_g = G.lam_off;
+    P.cp = F.p + G.p;
+    P.cq = F.q + G.q;
+    P.msa = c->geo.ms[ta];
+    P.msb = c->geo.ms[tb];
+    P.ksa = c->geo.ks[ta];
+    P.ksb = c->geo.ks[tb];
+    P.kla = sd.klo[ta];
+    P.klb = sd.klo[tb];
+    P.nea = sd.ne2[ta];
+    P.neb = sd.ne2[tb];
+    P.na = F.na;
+    P.nb = F.nb;
+    v.push_back(P);
+  }
+  if (v.empty()) return hipSuccess;
+  return hipMemcpy(c->d_expairs, v.data(), v.size() * sizeof(ExPair), hipMemcpyHostToDevice);
+}
+
 // ------------------------------------------------------------------ outer iteration pieces
 
 int enqueue_check(sos_ctx* c, double* phi) {
@@ -489,7 +532,7 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
-  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
+  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
   return SOS_OK;
 }
 
@@ -534,7 +577,7 @@ int stepwise_iteration(sos_ctx* c) {
     hipEventDestroy(e1);
   }
   HIPCHK(launch_add_correction(c->dev, L, c->fp32, c->u, c->x, c->scal, st));
-  HIPCHK(launch_exchange(c->dev, c->d_pairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
+  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
   return SOS_OK;
 }
 
@@ -972,7 +1015,8 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   }
   c->lds_limit = prop.sharedMemPerBlock;
   {
-    const size_t ex_lds = 2 * sizeof(double) * (size_t)(c->max_face_na + 4) * (size_t)(kExchangeRows + 4);
+    const size_t ex_lds =
+        2 * sizeof(double) * (size_t)(c->max_face_na + 4) * (size_t)(exchange_rows(c->max_face_na) + 4);
     if (ex_lds > c->lds_limit) {
       release(c);
       return fail(SOS_EINVAL, "interface face of %d nodes along its first axis needs %zu bytes of LDS (limit %zu)",
@@ -996,7 +1040,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   Dev tmp{nullptr, nullptr, g, 0, 0};
   c->n_norm_blocks = assemble_blocks(tmp, c->max_n);
   if ((rc = dalloc(&c->d_subs, c->subs.size())) || (rc = dalloc(&c->d_faces, c->faces.size())) ||
-      (rc = dalloc(&c->d_pairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||
+      (rc = dalloc(&c->d_expairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||
       (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
       (rc = dalloc(&c->u, c->n_local)) || (rc = dalloc(&c->f, c->n_local)) || (rc = dalloc(&c->lam, c->n_lam)) ||
       (rc = dalloc(&c->b, c->n_local)) ||
@@ -1039,8 +1083,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   if (e == hipSuccess) e = hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess && !c->faces.empty())
     e = hipMemcpy(c->d_faces, c->faces.data(), c->faces.size() * sizeof(FaceDesc), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !c->pairs.empty())
-    e = hipMemcpy(c->d_pairs, c->pairs.data(), c->pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = upload_expairs(c);
   if (e == hipSuccess) e = hipMemcpy(c->d_order, c->order.data(), c->order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(c->seg.d_blocks, c->seg.blocks.data(), c->seg.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice);
@@ -1069,6 +1112,7 @@ int sos_set_robin(sos_ctx* c, const sos_robin* robin) {
   hipError_t e = hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess && !c->faces.empty())
     e = hipMemcpy(c->d_faces, c->faces.data(), c->faces.size() * sizeof(FaceDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = upload_expairs(c);
   if (e != hipSuccess) return fail(SOS_EHIP, "set_robin copies: %s", hipGetErrorString(e));
   return SOS_OK;
 }

@@ -19,6 +19,7 @@ struct SegLaunch {
   int32_t cpt;              // x-y columns per thread (1 to 4)
   size_t lds64;             // dynamic LDS bytes for FP64 marches
   size_t lds32;             // dynamic LDS bytes for FP32 marches
+  int32_t zu;               // every block marches one segment (uniform-z residual)
 };
 
 struct Dev {
@@ -114,9 +115,26 @@ struct FusedArgs {
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st);
 // Robin exchange over all interfaces (in place, both directions).
-constexpr int kExchangeRows = 16;  // face rows per block of the exchange kernel
-hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_na,
-                           int32_t max_nb, const double* u, double* lam, hipStream_t st);
+// One interface pair (s <- j, j <- s) resolved on the host: where each side's
+// face nodes sit in the local vectors (node (a, b) at base + a sa + b sb, a
+// fastest), both lambda offsets, the summed coefficients and the tangential
+// 1D rows (shared by both sides).
+struct ExPair {
+  int64_t base_s, sa_s, sb_s, base_j, sa_j, sb_j;
+  int64_t lam_f, lam_g;  // lambda_{s<-j}, lambda_{j<-s}
+  double cp, cq;         // p_sj + p_js, q_sj + q_js
+  double msa, msb, ksa, ksb;
+  int32_t kla, klb, nea, neb, na, nb;
+};
+constexpr int kExchangeRows = 16;  // most face rows per block of the exchange kernel
+constexpr int kExThreads = 512;    // threads of an exchange block
+// Face rows per exchange block: as many as one pass of the block covers.
+inline int exchange_rows(int max_na) {
+  const int r = kExThreads / (max_na > 0 ? max_na : 1);
+  return r < 1 ? 1 : (r > kExchangeRows ? kExchangeRows : r);
+}
+hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
+                           double* lam, hipStream_t st);
 // Glue: utilde = average of copies (local layout).
 hipError_t launch_glue(const Dev& d, int max_n, const double* u, double* ut, hipStream_t st);
 // rho = f - K^N utilde (FP64, Neumann local stiffness).

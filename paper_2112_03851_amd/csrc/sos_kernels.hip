@@ -593,8 +593,10 @@ __global__ void k_face_sum(Dev d, const double* __restrict__ f, const double* __
 }
 
 // r = b - A u, b = f + sum_j R_sj^T lambda_{s<-j} (from k_face_sum); RZ:
-// also r'D^-1 r (the stepwise CG's first gamma).
-template <typename TO, int CPT, bool Q, bool RZ>
+// also r'D^-1 r (the stepwise CG's first gamma). ZU: every block marches one
+// segment (the host checks; otherwise the partials are NaN and the solve
+// reports a breakdown).
+template <typename TO, int CPT, bool Q, bool RZ, bool ZU = false>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
                                                    const double* __restrict__ b, TO* __restrict__ r,
                                                    double* __restrict__ part, double* __restrict__ team_part) {
@@ -611,6 +613,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   lds_zero(lds, sl.G * kPlanes * sl.SP);
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const bool bad = ZU && sl.G != 1;
   const double* __restrict__ ub = u + sl.off;
   const double* __restrict__ bb = b + sl.off;
   TO* __restrict__ rb = r + sl.off;
@@ -626,9 +629,10 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
     a1 += rd * rd;
     a2 += bv * bv;
   };
-  zmarch(sl, lds, fetch, make, store);
+  if (!bad) zmarch<ZU>(sl, lds, fetch, make, store);
   double acc[3] = {a0, a1, a2};
   block_sum(acc);
+  if (bad) acc[0] = acc[1] = acc[2] = __builtin_nan("");
   if (threadIdx.x == 0) {
     part[3 * blockIdx.x + 0] = acc[0];
     part[3 * blockIdx.x + 1] = acc[1];
@@ -1210,77 +1214,54 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
 
 // Position of face F's nodes in the concatenated local vectors: node (a, b)
 // of the face (first tangential axis fastest) is at base + a sa + b sb.
-struct FaceGeo {
-  int64_t base, sa, sb;
-  int kla, klb, nea, neb;
-  double msa, msb, ksa, ksb;
-};
-
-__device__ __forceinline__ FaceGeo face_geo(const Dev& d, const FaceDesc& F) {
-  const SubDesc& sd = d.subs[F.s];
-  const int ax = F.axis;
-  // tangential axes: x-face (y, z), y-face (x, z), z-face (x, y)
-  const int ta = ax == 0 ? 1 : 0, tb = ax == 2 ? 1 : 2;
-  FaceGeo g;
-  g.kla = sd.klo[ta];
-  g.klb = sd.klo[tb];
-  g.nea = sd.ne2[ta];
-  g.neb = sd.ne2[tb];
-  g.msa = d.geo.ms[ta];
-  g.msb = d.geo.ms[tb];
-  g.ksa = d.geo.ks[ta];
-  g.ksb = d.geo.ks[tb];
-  const int64_t st[3] = {1, sd.n[0], (int64_t)sd.n[0] * sd.n[1]};
-  g.sa = st[ta];
-  g.sb = st[tb];
-  const int plane = F.side ? sd.n[ax] - 1 : 0;
-  g.base = sd.off + (int64_t)plane * st[ax];
-  return g;
-}
-
-// One block per (interface pair, band of kExchangeRows face rows): both sides' face
-// values are gathered once into zero-padded LDS tiles (two halo rows and
-// columns: the tangential 1D rows reach +-2), then
+// One block per (interface pair, band of face rows): both sides' face values
+// are gathered once into zero-padded LDS tiles (two halo rows and columns: the
+// tangential 1D rows reach +-2), then
 //   lambda_{s<-j} <- -lambda_{j<-s} + (A_sj + A_js) u_j,
 //   lambda_{j<-s} <- -lambda_{s<-j} + (A_sj + A_js) u_s,   A = p M_F + q K_F,
-// with M_F = Ma (x) Mb and K_F = Ka (x) Mb + Ma (x) Kb (plain 1D factors).
-constexpr int kExThreads = 256;
-
-__global__ void __launch_bounds__(kExThreads) k_exchange(Dev d, const int32_t* __restrict__ pair_faces,
+// with M_F = Ma (x) Mb and K_F = Ka (x) Mb + Ma (x) Kb (plain 1D factors). The
+// pair's geometry comes resolved from the host (one descriptor load), and the
+// old lambda of a thread's first node is loaded together with the gather.
+__global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restrict__ pairs, int rows_max,
                                                          const double* __restrict__ u, double* __restrict__ lam) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* Us = reinterpret_cast<double*>(smem);
-  const FaceDesc F = d.faces[pair_faces[blockIdx.y]];
-  const int na = F.na, nb = F.nb;
-  const int b0 = blockIdx.x * kExchangeRows;
+  const ExPair P = pairs[blockIdx.y];
+  const int na = P.na, nb = P.nb;
+  const int b0 = blockIdx.x * rows_max;
   if (b0 >= nb) return;
-  const FaceDesc G = d.faces[F.opp];
-  const int rows = min(kExchangeRows, nb - b0);
+  const int rows = min(rows_max, nb - b0);
   const int W = na + 4, H = rows + 4;
   double* Uj = Us + W * H;
-  const FaceGeo gs = face_geo(d, F), gj = face_geo(d, G);
+  const int t0 = threadIdx.x;
+  double lf0 = 0.0, lg0 = 0.0;
+  if (t0 < na * rows) {
+    const int64_t t2 = (t0 % na) + (int64_t)na * (b0 + t0 / na);
+    lf0 = lam[P.lam_f + t2];
+    lg0 = lam[P.lam_g + t2];
+  }
   for (int e = threadIdx.x; e < W * H; e += blockDim.x) {
     const int a = e % W - 2, b = e / W + b0 - 2;
     double vs = 0.0, vj = 0.0;
     if (a >= 0 && a < na && b >= 0 && b < nb) {
-      vs = u[gs.base + a * gs.sa + b * gs.sb];
-      vj = u[gj.base + a * gj.sa + b * gj.sb];
+      vs = u[P.base_s + a * P.sa_s + b * P.sb_s];
+      vj = u[P.base_j + a * P.sa_j + b * P.sb_j];
     }
     Us[e] = vs;
     Uj[e] = vj;
   }
   __syncthreads();
-  const double cp = F.p + G.p, cq = F.q + G.q;
-  for (int t = threadIdx.x; t < na * rows; t += blockDim.x) {
+  // (A_sj + A_js) u_s and (A_sj + A_js) u_j at face node t of the band
+  auto apply = [&](int t, double& as, double& aj) {
     const int a = t % na, b = b0 + t / na;
-    // both subdomains share the tangential grid of the face
-    const Row<double> ra = row_of<double>(a + gs.kla, gs.nea, gs.ksa, gs.msa, 0.0, 0.0);
-    const Row<double> rb = row_of<double>(b + gs.klb, gs.neb, gs.ksb, gs.msb, 0.0, 0.0);
-    const double ma[5] = {ra.m2, 2.0 * gs.msa, ra.m0, 2.0 * gs.msa, ra.m2};
-    const double ka[5] = {ra.k2, -8.0 * gs.ksa, ra.k0, -8.0 * gs.ksa, ra.k2};
-    const double mb[5] = {rb.m2, 2.0 * gs.msb, rb.m0, 2.0 * gs.msb, rb.m2};
-    const double kb[5] = {rb.k2, -8.0 * gs.ksb, rb.k0, -8.0 * gs.ksb, rb.k2};
-    double as = 0.0, aj = 0.0;
+    const Row<double> ra = row_of<double>(a + P.kla, P.nea, P.ksa, P.msa, 0.0, 0.0);
+    const Row<double> rb = row_of<double>(b + P.klb, P.neb, P.ksb, P.msb, 0.0, 0.0);
+    const double ma[5] = {ra.m2, 2.0 * P.msa, ra.m0, 2.0 * P.msa, ra.m2};
+    const double ka[5] = {ra.k2, -8.0 * P.ksa, ra.k0, -8.0 * P.ksa, ra.k2};
+    const double mb[5] = {rb.m2, 2.0 * P.msb, rb.m0, 2.0 * P.msb, rb.m2};
+    const double kb[5] = {rb.k2, -8.0 * P.ksb, rb.k0, -8.0 * P.ksb, rb.k2};
+    as = 0.0;
+    aj = 0.0;
 #pragma unroll
     for (int ob = 0; ob < 5; ++ob) {
       const double* rs = Us + (b - b0 + ob) * W + a;
@@ -1293,14 +1274,24 @@ __global__ void __launch_bounds__(kExThreads) k_exchange(Dev d, const int32_t* _
         mj += ma[oa] * rj[oa];
         kj += ka[oa] * rj[oa];
       }
-      as += cp * mb[ob] * ms_ + cq * (kb[ob] * ms_ + mb[ob] * ks_);
-      aj += cp * mb[ob] * mj + cq * (kb[ob] * mj + mb[ob] * kj);
+      as += P.cp * mb[ob] * ms_ + P.cq * (kb[ob] * ms_ + mb[ob] * ks_);
+      aj += P.cp * mb[ob] * mj + P.cq * (kb[ob] * mj + mb[ob] * kj);
     }
-    const int64_t t2 = a + (int64_t)na * b;
-    const double lf = lam[F.lam_off + t2];
-    const double lg = lam[G.lam_off + t2];
-    lam[F.lam_off + t2] = -lg + aj;
-    lam[G.lam_off + t2] = -lf + as;
+    return (int64_t)a + (int64_t)na * b;
+  };
+  if (t0 < na * rows) {
+    double as, aj;
+    const int64_t t2 = apply(t0, as, aj);
+    lam[P.lam_f + t2] = -lg0 + aj;
+    lam[P.lam_g + t2] = -lf0 + as;
+  }
+  for (int t = t0 + blockDim.x; t < na * rows; t += blockDim.x) {
+    double as, aj;
+    const int64_t t2 = apply(t, as, aj);
+    const double lf = lam[P.lam_f + t2];
+    const double lg = lam[P.lam_g + t2];
+    lam[P.lam_f + t2] = -lg + aj;
+    lam[P.lam_g + t2] = -lf + as;
   }
 }
 
@@ -1572,6 +1563,10 @@ hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, 
   if (fp32 && rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
                                                L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_part));
+  } else if (fp32 && L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false, true>), dim3(L.nblocks),
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, b, (float*)r_out, part,
+                                               team_part));
   } else if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
                                                L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_part));
@@ -1695,12 +1690,13 @@ hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threa
   return hipSuccess;
 }
 
-hipError_t launch_exchange(const Dev& d, const int32_t* pair_faces, int32_t n_pairs, int32_t max_na,
-                           int32_t max_nb, const double* u, double* lam, hipStream_t st) {
+hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
+                           double* lam, hipStream_t st) {
   if (n_pairs == 0) return hipSuccess;
-  const size_t lds = 2 * sizeof(double) * (size_t)(max_na + 4) * (size_t)(kExchangeRows + 4);
-  hipLaunchKernelGGL(k_exchange, dim3((max_nb + kExchangeRows - 1) / kExchangeRows, n_pairs), dim3(kExThreads), lds, st, d,
-                     pair_faces, u, lam);
+  const int rows = exchange_rows(max_na);
+  const size_t lds = 2 * sizeof(double) * (size_t)(max_na + 4) * (size_t)(rows + 4);
+  hipLaunchKernelGGL(k_exchange, dim3((max_nb + rows - 1) / rows, n_pairs), dim3(kExThreads), lds, st, pairs, rows, u,
+                     lam);
   return hipGetLastError();
 }
 

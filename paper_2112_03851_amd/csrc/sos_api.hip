@@ -60,7 +60,7 @@ struct sos_ctx {
   std::vector<int32_t> pairs;
   std::vector<int32_t> order;
   int64_t n_local = 0, n_lam = 0, n_nodes = 0;
-  int max_n = 0, max_face = 0, max_face_na = 0, max_face_nb = 0, max_shell = 0;
+  int max_n = 0, max_face = 0, max_face_na = 0, max_face_nb = 0;
   Dev dev{};
   SubDesc* d_subs = nullptr;
   FaceDesc* d_faces = nullptr;
@@ -526,8 +526,7 @@ hipError_t copy_load_to_rhs(sos_ctx* c) {
 // One outer iteration in the batched form; ev (optional) brackets the fused kernel.
 int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
-  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
-  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->b, c->r, c->part,
+  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
                          c->fused_team > 1 ? c->team_part : nullptr, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
@@ -540,8 +539,7 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
 int stepwise_iteration(sos_ctx* c) {
   hipStream_t st = c->stream;
   const SegLaunch& L = c->seg.L;
-  HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
-  HIPCHK(launch_residual(c->dev, L, c->fp32, true, c->u, c->b, c->r, c->part, nullptr, st));
+  HIPCHK(launch_residual(c->dev, L, c->fp32, true, c->u, c->f, c->lam, c->b, c->r, c->part, nullptr, st));
   HIPCHK(launch_cg_init(c->dev, L, c->part, c->opts.inner_tol, c->opts.inner_abs, c->scal, c->ndone, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.timing) {
@@ -751,8 +749,7 @@ int autotune(sos_ctx* c) {
       bool ok = true;
       for (int rep = 0; rep < 2 && ok; ++rep) {
         HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
-        HIPCHK(launch_face_sum(c->dev, c->max_shell, c->f, c->lam, c->b, st));
-        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->b, c->r, c->part,
+        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
                                team > 1 ? c->team_part : nullptr, st));
         HIPCHK(hipEventRecord(e0, st));
         if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
@@ -922,12 +919,6 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
         d.off = off;
         off = align64(off + n);
         c->max_n = std::max<int>(c->max_n, (int)n);
-        {  // boundary-shell nodes, counted as the face-sum kernel enumerates them
-          const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
-          const int ix = std::max(nx - 2, 0), iy = std::max(ny - 2, 0);
-          const int shell = (nx > 1 ? 2 : 1) * ny * nz + (ny > 1 ? 2 : 1) * ix * nz + (nz > 1 ? 2 : 1) * ix * iy;
-          c->max_shell = std::max(c->max_shell, shell);
-        }
       }
   c->n_local = off;
   // directed faces: by s, axis, side

@@ -67,16 +67,14 @@ hipError_t launch_load_density(const Dev& d, int max_n, const double* drho, doub
 // f_s = f_nodes / multiplicity.
 hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, double* f_loc,
                              hipStream_t st);
-// b = f + sum_j R_sj^T lambda_{s<-j} at the boundary shell nodes of every
-// subdomain (elsewhere b keeps its value, b = f).
-hipError_t launch_face_sum(const Dev& d, int max_shell, const double* f, const double* lam, double* b,
-                           hipStream_t st);
-// r = b - A u (FP64 apply), stored as Tr; partials (r'D^-1 r if rz, else 0),
-// r'r, b'b per block.
+// b = f + sum_j R_sj^T lambda_{s<-j} rewritten at the boundary shell nodes
+// (elsewhere b keeps its value, b = f), then r = b - A u (FP64 apply), stored
+// as Tr; partials (r'D^-1 r if rz, else 0), r'r, b'b per block.
 // team_part (optional): the fused kernel's team slots, n_sub * kMaxTeam * 8
 // doubles, cleared for the launch that follows.
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u,
-                           const double* b, void* r_out, double* part, double* team_part, hipStream_t st);
+                           const double* f, const double* lam, double* b, void* r_out, double* part,
+                           double* team_part, hipStream_t st);
 // Per-subdomain CG scalars from the residual partials (stepwise path).
 hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel,
                           double tol_abs, CgScal* scal, int32_t* ndone, hipStream_t st);

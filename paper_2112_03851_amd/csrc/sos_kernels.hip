@@ -557,48 +557,54 @@ __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int
 
 // ---------------------------------------------------------------------------- outer kernels
 
-// r = f + sum_F R^T lambda_F - A u, rounded to TO; partials (r'D^-1 r, r'r, b'b).
-// b = f + sum_j R_sj^T lambda_{s<-j} on the boundary shell of every subdomain
-// (each shell node written once; off the shell b = f is left as it is).
-__global__ void k_face_sum(Dev d, const double* __restrict__ f, const double* __restrict__ lam,
-                           double* __restrict__ b) {
-  const SubDesc sd = d.subs[blockIdx.y];
-  const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2];
-  const int xs = nx > 1 ? 2 : 1, ys = ny > 1 ? 2 : 1, zs = nz > 1 ? 2 : 1;
-  const int ix = max(nx - 2, 0), iy = max(ny - 2, 0);
-  const int n_x = xs * ny * nz, n_y = ys * ix * nz, n_z = zs * ix * iy;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (t < n_x) {  // x planes: all (j, k)
-    const int side = t / (ny * nz), e = t % (ny * nz);
-    i = side ? nx - 1 : 0;
-    j = e % ny;
-    k = e / ny;
-  } else if ((t -= n_x) < n_y) {  // y planes: interior i, all k
-    const int side = t / (ix * nz), e = t % (ix * nz);
-    j = side ? ny - 1 : 0;
-    i = 1 + e % ix;
-    k = e / ix;
-  } else if ((t -= n_y) < n_z) {  // z planes: interior i and j
-    const int side = t / (ix * iy), e = t % (ix * iy);
-    k = side ? nz - 1 : 0;
-    i = 1 + e % ix;
-    j = 1 + e / ix;
-  } else {
-    return;
-  }
+// b = f + sum_j R_sj^T lambda_{s<-j} on the boundary-shell nodes of planes
+// [z0, z1) of subdomain sd (off the shell b = f is left as it is): the z-face
+// planes whole, the other planes' perimeters; every node is written by the
+// block that owns its plane.
+__device__ __forceinline__ void shell_rhs(const Dev& d, const SubDesc& sd, int z0, int z1,
+                                          const double* __restrict__ f, const double* __restrict__ lam,
+                                          double* __restrict__ b) {
+  const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2], S = nx * ny;
+  const int xs = nx > 1 ? 2 : 1, ys = ny > 1 ? 2 : 1, ix = max(nx - 2, 0);
+  const int perim = xs * ny + ys * ix;
+  const int nzf = (z0 == 0 ? 1 : 0) + (z1 == nz && nz - 1 != 0 ? 1 : 0);  // z-face planes in range
+  const int k0 = z0 == 0 ? 1 : z0, k1 = z1 == nz ? nz - 1 : z1;            // perimeter-only planes
+  const int n_face = nzf * S, total = n_face + max(k1 - k0, 0) * perim;
   const LamOff L = lam_offsets(d, sd);
-  const int64_t idx = sd.off + i + (int64_t)nx * (j + (int64_t)ny * k);
-  b[idx] = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
+#pragma unroll 4
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int i, j, k;
+    if (t < n_face) {
+      k = (t < S && z0 == 0) ? 0 : nz - 1;
+      const int e = t % S;
+      i = e % nx;
+      j = e / nx;
+    } else {
+      const int q = (t - n_face) / perim, e = (t - n_face) - q * perim;
+      k = k0 + q;
+      if (e < xs * ny) {
+        i = e < ny ? 0 : nx - 1;
+        j = e < ny ? e : e - ny;
+      } else {
+        const int e2 = e - xs * ny;
+        j = e2 < ix ? 0 : ny - 1;
+        i = 1 + (e2 < ix ? e2 : e2 - ix);
+      }
+    }
+    const int64_t idx = sd.off + i + (int64_t)nx * (j + (int64_t)ny * k);
+    b[idx] = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
+  }
 }
 
-// r = b - A u, b = f + sum_j R_sj^T lambda_{s<-j} (from k_face_sum); RZ:
-// also r'D^-1 r (the stepwise CG's first gamma). ZU: every block marches one
-// segment (the host checks; otherwise the partials are NaN and the solve
-// reports a breakdown).
+// r = b - A u with b = f + sum_j R_sj^T lambda_{s<-j}: each block first
+// rewrites b on the shell nodes of its own planes (the march uses b only
+// there, and at its own interior nodes b = f is kept); RZ: also r'D^-1 r (the
+// stepwise CG's first gamma). ZU: every block marches one segment (the host
+// checks; otherwise the partials are NaN and the solve reports a breakdown).
 template <typename TO, int CPT, bool Q, bool RZ, bool ZU = false>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
-                                                   const double* __restrict__ b, TO* __restrict__ r,
+                                                   const double* __restrict__ f, const double* __restrict__ lam,
+                                                   double* __restrict__ b, TO* __restrict__ r,
                                                    double* __restrict__ part, double* __restrict__ team_part) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* lds = reinterpret_cast<double*>(smem);
@@ -608,9 +614,11 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
     for (int i = threadIdx.x; i < d.geo.n_sub * kMaxTeam * 2 * 4; i += blockDim.x) team_part[i] = 0.0;
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
+  shell_rhs(d, sd, bd.z0, bd.z1, f, lam, b);
   Slots<double, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * kPlanes * sl.SP);
+  // the block's b writes are visible to its own march after the barrier
   __syncthreads();
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const bool bad = ZU && sl.G != 1;
@@ -1550,32 +1558,26 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
   return hipGetLastError();
 }
 
-hipError_t launch_face_sum(const Dev& d, int max_shell, const double* f, const double* lam, double* b,
+hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u, const double* f,
+                           const double* lam, double* b, void* r_out, double* part, double* team_part,
                            hipStream_t st) {
-  if (max_shell <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_face_sum, dim3((max_shell + 255) / 256, d.geo.n_sub), dim3(256), 0, st, d, f, lam, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u, const double* b,
-                           void* r_out, double* part, double* team_part, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
   if (fp32 && rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part, team_part));
   } else if (fp32 && L.zu) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false, true>), dim3(L.nblocks),
-                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, b, (float*)r_out, part,
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part,
                                                team_part));
   } else if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (float*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part, team_part));
   } else if (rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, (double*)r_out, part, team_part));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, b, (double*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, (double*)r_out, part, team_part));
   }
   });
   return hipGetLastError();

@@ -122,10 +122,10 @@ typedef struct {
                           64 x cols columns cannot cover every subdomain's
                           plane that way); the autotuner tries both forms  */
   int32_t resident;    /* 1 (default): the FP32 fused kernel may keep the CG
-                          direction p and the correction x in LDS for the
-                          whole launch where they fit (uniform z-ranges;
-                          with block != 0 it does, the autotuner tries both);
-                          0: never                                          */
+                          direction p and the correction x (or x alone) in
+                          LDS for the whole launch where they fit (uniform
+                          z-ranges; with block != 0 it does, the autotuner
+                          tries both); 0: never                             */
 } sos_opts;
 
 typedef struct {
@@ -148,7 +148,8 @@ typedef struct {
   int32_t team;           /* blocks per subdomain of the fused CG kernel        */
   int32_t wave_rows;      /* 1: each wave of the fused CG kernel owns whole
                              x-rows of the plane (one barrier per plane)       */
-  int32_t resident;       /* 1: the fused CG kernel keeps p and x in LDS        */
+  int32_t resident;       /* the fused CG kernel keeps in LDS: 1 p and x,
+                             2 x alone (p and x do not fit), 0 neither         */
 } sos_stats;
 
 /* Fill *opts with defaults for the given precision. */

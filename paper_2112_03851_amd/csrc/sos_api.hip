@@ -334,18 +334,22 @@ std::vector<Shape> fused_candidates(const sos_ctx* c) {
     const size_t n = out.size();
     for (size_t i = 0; i < n; ++i) out.push_back({out[i].threads, out[i].cpt, out[i].ra, 1});
   }
+  // (shapes with res = 1 keep p and x in LDS, or x alone where both do not fit)
   return out;
 }
 
-// LDS bytes of the resident p and x of the fused kernel: the largest z-range
-// of a team member times its plane, two FP32 values per node.
-size_t fused_res_bytes(const sos_ctx* c) {
+// LDS bytes of a resident fused-kernel block (one segment): the march planes
+// plus, per node of the largest z-range of a team member, `words` FP32 values
+// (2: p and x, 1: x).
+size_t fused_res_lds(const sos_ctx* c, int words) {
   size_t need = 0;
   const int T = c->fused_team;
+  const int planes = march_planes(c->dev.hasq != 0, c->fused_ra != 0);
   for (auto& s : c->subs)
     for (int tau = 0; tau < T; ++tau) {
       const size_t zlen = (size_t)(((tau + 1) * s.n[2]) / T - (tau * s.n[2]) / T);
-      need = std::max(need, 2 * zlen * (size_t)s.n[0] * (size_t)s.n[1] * sizeof(float));
+      const size_t sp = (size_t)(s.n[0] + 2 * kPad) * (size_t)(s.n[1] + 2 * kPad);
+      need = std::max(need, (planes * sp + words * zlen * (size_t)s.n[0] * (size_t)s.n[1]) * sizeof(float));
     }
   return need;
 }
@@ -505,13 +509,16 @@ FusedArgs fused_args(sos_ctx* c) {
   a.team_part = c->team_part;
   a.zu = fused_one_segment(c) ? 1 : 0;
   a.rows = c->fused_ra;
+  // resident p and x where they fit, else x alone, else neither
   a.res = 0;
   a.lds_bytes = (uint32_t)c->fused_lds;
   if (c->fused_res && c->fp32 && a.zu) {
-    const size_t total = c->fused_lds + fused_res_bytes(c);
-    if (total <= c->lds_limit) {
-      a.res = 1;
-      a.lds_bytes = (uint32_t)total;
+    for (int words = 2; words >= 1 && !a.res; --words) {
+      const size_t total = std::max(fused_res_lds(c, words), c->fused_lds);
+      if (total <= c->lds_limit) {
+        a.res = words == 2 ? 1 : 2;
+        a.lds_bytes = (uint32_t)total;
+      }
     }
   }
   return a;

@@ -54,6 +54,9 @@ __host__ __device__ inline int ra_waves(int nx, int ny, int cpt) {
 // LDS planes per march segment: the operand (two, alternating by step) and the
 // two y-pass results, each zero-padded by kPad.
 constexpr int kPlanes = 4;
+// LDS planes a single-segment march uses: the second operand plane only with
+// second-order face terms or wave-owned rows.
+__host__ __device__ inline int march_planes(bool q, bool rows) { return (q || rows) ? kPlanes : kPlanes - 1; }
 // LDS bytes of such a march.
 __host__ __device__ inline size_t march_lds_bytes(int nx, int ny, int zlen, int threads, int cpt,
                                                   size_t elem) {
@@ -105,7 +108,7 @@ struct FusedArgs {
                                     // the residual kernel before each launch)
   int32_t zu;                       // every block marches one segment (uniform z variant)
   int32_t rows;                     // wave-owned rows (see ra_rows): one barrier per plane
-  int32_t res;                      // p and x resident in LDS (FP32, uniform z only)
+  int32_t res;                      // resident in LDS (FP32, uniform z only): 1 p and x, 2 x
   uint32_t lds_bytes;               // dynamic LDS of the launch (march planes + resident p, x)
 };
 // lds: the march planes; with a.res the launch takes a.lds_bytes (march planes

@@ -383,9 +383,11 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
   const int PX = sl.PX, SP = sl.SP;
   auto one_step = [&](auto ucst, int step) {
     constexpr int U = decltype(ucst)::value;
-    // the operand plane alternates between two LDS planes: the next step's
-    // writes never meet this step's x-pass reads of it (second-order terms)
-    const int po = (step & 1) ? 3 * SP : 0;
+    // with second-order terms (the x-pass reads the operand plane) or
+    // wave-owned rows (no barrier after the y-pass) the operand plane
+    // alternates between two LDS planes, so the next step's writes never meet
+    // this step's reads; otherwise the barrier after the y-pass orders them
+    const int po = ((Q || sl.ra) && (step & 1)) ? 3 * SP : 0;
     bool inr[CPT];
     int kp[CPT];
 #pragma unroll
@@ -897,6 +899,10 @@ template <typename T>
 struct Three {
   T r, w, s;
 };
+template <typename T>
+struct Four {
+  T r, w, s, p;
+};
 
 // Sum the block partials of the T members of a team (the blocks that share
 // one subdomain). Every store of the block's sweep completes first (the halo
@@ -982,11 +988,12 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 // whose halo planes the team members read is coherent (ld_coh / st_coh), so
 // the team barrier needs no cache maintenance; a fixed instruction form on
 // every plane keeps the prefetch waits exact.
-// RES: p and x stay in LDS for the whole launch (uniform z only). A halo plane
-// only needs u = D^-1 (r - alpha (w + beta s)), so p and x are read and
-// written by the thread that owns the node and never by another block; global
-// traffic per CG iteration drops from ten words per node to six.
-template <typename T, int CPT, bool Q, bool ZU, bool COH, bool RES>
+// RES (uniform z only): 1, p and x stay in LDS for the whole launch; 2, x
+// alone (for z-ranges where both do not fit). A halo plane only needs
+// u = D^-1 (r - alpha (w + beta s)), so p and x are read and written by the
+// thread that owns the node and never by another block; global traffic per CG
+// iteration drops from ten words per node to six (eight with x alone).
+template <typename T, int CPT, bool Q, bool ZU, bool COH, int RES>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
@@ -1027,14 +1034,18 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     bb += a.res_part[3 * b + 2];
   }
   const double stop2 = fmax(a.tol_rel * a.tol_rel * rr, a.tol_abs * a.tol_abs * bb);
-  lds_zero(lds, sl.G * kPlanes * sl.SP);
+  // march planes: the second operand plane only with second-order terms or
+  // wave-owned rows (see zmarch)
+  const int mplanes = RES ? march_planes(Q, ra) : kPlanes;
+  lds_zero(lds, sl.G * mplanes * sl.SP);
   __syncthreads();
-  // resident p and x: one LDS value per own node, index li - S uz0
-  T* const pres = lds + sl.G * kPlanes * sl.SP;
-  T* const xres = pres + (size_t)(zb1 - zb0) * sl.S;
+  // resident p (RES 1) and x: one LDS value per own node, index li - S uz0
+  T* const xres = lds + sl.G * mplanes * sl.SP;
+  T* const pres = xres + (size_t)(zb1 - zb0) * sl.S;
   const uint32_t plane0 = (uint32_t)(sl.S * zb0);
   int t = 0, brk = 0;
-  if (RES && (!ZU || (size_t)(sl.G * kPlanes * sl.SP + 2 * (zb1 - zb0) * sl.S) * sizeof(T) > a.lds_bytes))
+  if (RES && (!ZU || (size_t)(sl.G * mplanes * sl.SP + (RES == 1 ? 2 : 1) * (zb1 - zb0) * sl.S) * sizeof(T) >
+                         a.lds_bytes))
     brk = 1;  // the host sizes the LDS for the largest z-range
   if (COH != (TM > 1)) brk = 1;  // the host pairs the coherent variant with teams
   if (!isfinite(rr)) brk = 1;
@@ -1085,7 +1096,20 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       // combined across the block in FP64
       T ag = T(0), ad = T(0), ar = T(0);
       auto fetch = [=](uint32_t li, bool) {
-        if constexpr (RES) {
+        if constexpr (RES == 2) {
+          Four<T> v;
+          if constexpr (COH) {
+            v.r = ld_coh(&at(rc, li));
+            v.w = ld_coh(&at(wc, li));
+            v.s = ld_coh(&at(sc, li));
+          } else {
+            v.r = at(rc, li);
+            v.w = at(wc, li);
+            v.s = at(sc, li);
+          }
+          v.p = at(pc, li);  // p: own planes only, never exchanged
+          return v;
+        } else if constexpr (RES == 1) {
           Three<T> v;
           if constexpr (COH) {
             v.r = ld_coh(&at(rc, li));
@@ -1121,11 +1145,17 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         const T sn = v.w + tb * vs;
         const T rn = v.r - ta * sn;
         const T un = dinv * rn;
-        if constexpr (RES) {
+        if constexpr (RES != 0) {
           if (own) {
             const uint32_t q = li - plane0;
-            const T pn = fma(tb, first ? T(0) : pres[q], dinv * v.r);
-            pres[q] = pn;
+            T pn;
+            if constexpr (RES == 1) {
+              pn = fma(tb, first ? T(0) : pres[q], dinv * v.r);
+              pres[q] = pn;
+            } else {
+              pn = fma(tb, first ? T(0) : v.p, dinv * v.r);
+              at(pn_, li) = pn;
+            }
             xres[q] = fma(ta, pn, first ? T(0) : xres[q]);
             if constexpr (COH) {
               st_coh(&at(sn_, li), sn);
@@ -1200,7 +1230,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         for (int u = 0; u < 4; ++u)
           if (k + u < sl.z1[m]) {
             const uint32_t li = sl.c[m] + sl.S * (k + u);
-            xv[u] = RES ? xres[li - plane0] : at(xb, li);
+            xv[u] = RES != 0 ? xres[li - plane0] : at(xb, li);
             uv[u] = at(ub, li);
           }
 #pragma unroll
@@ -1648,7 +1678,7 @@ static bool team_grid_resident(const void* fn, int threads, size_t lds, int bloc
   return (long long)per_cu * cus >= blocks;
 }
 
-template <typename T, int C, bool Q, bool ZU, bool RES = false>
+template <typename T, int C, bool Q, bool ZU, int RES = 0>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
                                    hipStream_t st) {
   const dim3 grid(d.geo.n_sub * a.team), block(threads);
@@ -1677,8 +1707,10 @@ hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threa
                            const FusedArgs& a, hipStream_t st) {
   if (a.res && (!fp32 || !a.zu || lds > a.lds_bytes)) return hipErrorInvalidValue;
   SOS_DISPATCH_Q(d.hasq, {
-    if (fp32 && a.zu && a.res) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, true>(d, L, threads, a.lds_bytes, a, st)));
+    if (fp32 && a.zu && a.res == 1) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 1>(d, L, threads, a.lds_bytes, a, st)));
+    } else if (fp32 && a.zu && a.res == 2) {
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 2>(d, L, threads, a.lds_bytes, a, st)));
     } else if (fp32 && a.zu) {
       SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true>(d, L, threads, lds, a, st)));
     } else if (fp32) {

@@ -1,5 +1,5 @@
-"""The FP32 fused CG kernel with the direction p and the correction x resident
-in LDS (needs an MI355X).
+"""The FP32 fused CG kernel with the direction p and the correction x (or x
+alone) resident in LDS (needs an MI355X).
 
 Each node's p and x are read and written only by the thread that owns the
 node, in the same order and precision as through global memory, so a solve
@@ -18,6 +18,8 @@ from synth import workload
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 PLANE33 = dict(ne=(32, 16, 6), bc=(1, 1, 1, 1, 0, 0), cuts=((16,), (), (3,)), p=200.0)
+# 33x33x31-node subdomains: p and x need 270 KB with the march planes, x alone 152 KB
+TALL33 = dict(ne=(32, 16, 16), bc=(1, 1, 1, 1, 0, 0), cuts=((16,), (), ()), p=200.0)
 
 
 def _torch():
@@ -25,13 +27,15 @@ def _torch():
     return torch
 
 
-# (case, block, team, wave_rows)
+# (case, block, team, wave_rows, residency level when allowed: 1 p and x, 2 x)
 SOLVES = {
-    "c1_team1": ("c1", 256, 1, 0),
-    "c1_team4": ("c1", 256, 4, 0),
-    "c1_team2_wave_rows": ("c1", 384, 2, 1),
-    "plane33_team2": (PLANE33, 576, 2, 0),
-    "plane33_cols3_wave_rows": (PLANE33, 448, 1, 1),
+    "c1_team1": ("c1", 256, 1, 0, 1),
+    "c1_team4": ("c1", 256, 4, 0, 1),
+    "c1_team2_wave_rows": ("c1", 384, 2, 1, 1),
+    "plane33_team2": (PLANE33, 576, 2, 0, 1),
+    "plane33_cols3_wave_rows": (PLANE33, 448, 1, 1, 1),
+    "tall33_x_alone": (TALL33, 576, 1, 0, 2),
+    "tall33_team2": (TALL33, 576, 2, 0, 1),
 }
 
 
@@ -46,7 +50,7 @@ def _case(spec):
 @pytest.mark.parametrize("name", sorted(SOLVES))
 def test_resident_solve_is_bitwise_the_global_one(name):
     torch = _torch()
-    spec, block, team, rows = SOLVES[name]
+    spec, block, team, rows, level = SOLVES[name]
     case, drho, tol = _case(spec)
     f, _ = case.density_loads(drho)
     d = torch.tensor(drho, device="cuda")
@@ -54,7 +58,7 @@ def test_resident_solve_is_bitwise_the_global_one(name):
     for res in (0, 1):
         prob = case.problem(precision="fp32", mode="batched", block=block, team=team, wave_rows=rows, resident=res)
         phi, st = prob.solve(d, tol)
-        assert st["resident"] == res and st["team"] == team and st["converged"], (name, res, st)
+        assert st["resident"] == (level if res else 0) and st["team"] == team and st["converged"], (name, res, st)
         out[res] = (phi.cpu().numpy(), st)
         prob.close()
     (p0, s0), (p1, s1) = out[0], out[1]
@@ -92,8 +96,8 @@ def test_resident_one_outer_iteration_matches_oracle():
 
 
 def test_resident_falls_back_where_p_and_x_do_not_fit():
-    """33x33x39-node subdomains in one block need 340 KB for p and x: the
-    kernel keeps them in global memory and still solves."""
+    """33x33x39-node subdomains in one block need 186 KB for x alone with the
+    march planes: the kernel keeps p and x in global memory and still solves."""
     torch = _torch()
     case = Case(ne=(32, 16, 20), bc=(1, 1, 1, 1, 0, 0), cuts=((16,), (), ()), p=200.0)
     assert all(s.shape == (33, 33, 39) for s in case.part.subs)

@@ -617,9 +617,14 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
   c->kernel_launches = 0;
   const bool batched = c->opts.mode == SOS_BATCHED;
   // HIP events recorded inside a graph cannot be read back with
-  // hipEventElapsedTime: timed runs launch eagerly; so do team launches
-  // (cooperative launches are not captured)
-  const bool graph = batched && c->opts.use_graph && !c->opts.timing && c->fused_team == 1;
+  // hipEventElapsedTime: timed runs launch eagerly; so do cooperative team
+  // launches (not captured)
+  bool plain = c->fused_team == 1;
+  if (batched && !plain &&
+      launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
+                      c->stream, &plain) != hipSuccess)
+    plain = false;
+  const bool graph = batched && c->opts.use_graph && !c->opts.timing && plain;
   const int every = c->opts.check_every;
   int done = 0, checks = 0;
   double res = INFINITY, best = INFINITY;

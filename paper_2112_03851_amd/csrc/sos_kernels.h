@@ -112,9 +112,12 @@ struct FusedArgs {
   uint32_t lds_bytes;               // dynamic LDS of the launch (march planes + resident p, x)
 };
 // lds: the march planes; with a.res the launch takes a.lds_bytes (march planes
-// and the resident p and x of the largest z-range, at least lds).
+// and the resident p and x of the largest z-range, at least lds). A team
+// launch is a plain one when the kernel's occupancy admits the whole grid,
+// else cooperative. plain != NULL: launch nothing, report whether the launch
+// would be plain (and so can be captured in a graph).
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
-                           const FusedArgs& a, hipStream_t st);
+                           const FusedArgs& a, hipStream_t st, bool* plain = nullptr);
 // Robin exchange over all interfaces (in place, both directions).
 // One interface pair (s <- j, j <- s) resolved on the host: where each side's
 // face nodes sit in the local vectors (node (a, b) at base + a sa + b sb, a

@@ -1669,19 +1669,36 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
 }
 
 // True when the device's compute units can hold all `blocks` blocks of the
-// kernel at once (occupancy of the kernel alone, dynamic LDS included).
+// kernel at once (occupancy of the kernel alone, dynamic LDS included). The
+// answer for the last (device, kernel, shape) is kept per host thread: the
+// same launch repeats every outer iteration.
 static bool team_grid_resident(const void* fn, int threads, size_t lds, int blocks) {
+  struct Memo {
+    int dev = -1, threads = 0, blocks = 0;
+    const void* fn = nullptr;
+    size_t lds = 0;
+    bool ok = false;
+  };
+  static thread_local Memo memo;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (memo.dev == dev && memo.fn == fn && memo.threads == threads && memo.lds == lds && memo.blocks == blocks)
+    return memo.ok;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return false;
-  return (long long)per_cu * cus >= blocks;
+  memo = {dev, threads, blocks, fn, lds, (long long)per_cu * cus >= blocks};
+  return memo.ok;
 }
 
 template <typename T, int C, bool Q, bool ZU, int RES = 0>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
-                                   hipStream_t st) {
+                                   hipStream_t st, bool* plain) {
   const dim3 grid(d.geo.n_sub * a.team), block(threads);
+  if (plain) {  // query only: would the launch be a plain one?
+    *plain = a.team <= 1 ||
+             team_grid_resident((const void*)k_fused_cg<T, C, Q, ZU, true, RES>, threads, lds, (int)grid.x);
+    return hipSuccess;
+  }
   if (a.team <= 1) {
     hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, false, RES>), grid, block, lds, st, d, L.bfirst, a);
     return hipGetLastError();
@@ -1704,21 +1721,21 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
 }
 
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
-                           const FusedArgs& a, hipStream_t st) {
+                           const FusedArgs& a, hipStream_t st, bool* plain) {
   if (a.res && (!fp32 || !a.zu || lds > a.lds_bytes)) return hipErrorInvalidValue;
   SOS_DISPATCH_Q(d.hasq, {
     if (fp32 && a.zu && a.res == 1) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 1>(d, L, threads, a.lds_bytes, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 1>(d, L, threads, a.lds_bytes, a, st, plain)));
     } else if (fp32 && a.zu && a.res == 2) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 2>(d, L, threads, a.lds_bytes, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 2>(d, L, threads, a.lds_bytes, a, st, plain)));
     } else if (fp32 && a.zu) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true>(d, L, threads, lds, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true>(d, L, threads, lds, a, st, plain)));
     } else if (fp32) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, false>(d, L, threads, lds, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, false>(d, L, threads, lds, a, st, plain)));
     } else if (a.zu) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, true>(d, L, threads, lds, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, true>(d, L, threads, lds, a, st, plain)));
     } else {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, false>(d, L, threads, lds, a, st)));
+      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, false>(d, L, threads, lds, a, st, plain)));
     }
   });
   return hipSuccess;

@@ -176,15 +176,20 @@ def test_fixed_point_equals_direct_solution_ragged_partition():
         assert st["converged"] and err <= 1e-8
 
 
-def test_batched_is_deterministic_and_graph_matches_eager():
+@pytest.mark.parametrize("team", [0, 4])
+def test_batched_is_deterministic_and_graph_matches_eager(team):
+    """Two solves and an eager solve agree bit for bit; team 0 autotunes, team
+    4 replays plain team launches (tagged barrier, residual clearing the team
+    slots) from the graph."""
     torch = _torch()
     wl = workload("c1", seed=1)
     case = Case.from_workload(wl)
     drho = torch.tensor(wl.drho(), device="cuda")
-    a = case.problem(precision="fp32", mode="batched", check_every=4)
+    kw = dict(team=4, block=256) if team else {}
+    a = case.problem(precision="fp32", mode="batched", check_every=4, **kw)
     p1, s1 = a.solve(drho, wl.tol)
     p2, s2 = a.solve(drho, wl.tol)
-    b = case.problem(precision="fp32", mode="batched", check_every=4, use_graph=0)
+    b = case.problem(precision="fp32", mode="batched", check_every=4, use_graph=0, **kw)
     p3, s3 = b.solve(drho, wl.tol)
     assert torch.equal(p1, p2) and torch.equal(p1, p3)
     assert s1["outer_iters"] == s2["outer_iters"] == s3["outer_iters"]

@@ -270,6 +270,7 @@ def main():
     batched = {"outer_iters": tot["outer_iters"] // args.steps, "inner_iters": tot["inner_iters"] // args.steps,
                "rel_residual": st["rel_residual"], "block": st["block"],
                "cols_per_thread": st["cols_per_thread"], "team": st["team"], "wave_rows": st["wave_rows"],
+               "resident": st["resident"],
                "seconds_per_solve": el / args.steps,
                "inner_tol": args.inner_tol, "check_every": args.check_every}
     prob.close()

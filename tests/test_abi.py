@@ -24,6 +24,7 @@ def test_opts_defaults():
     assert o.inner_abs == 1e-10 and o.inner_tol == 0.0 and o.G == 6.672e-11
     o = sos.default_opts(sos.SOS_FP32_INNER)
     assert o.mode == sos.SOS_BATCHED and o.inner_tol == 1e-2 and o.use_graph == 1
+    assert o.wave_rows == 0 and o.resident == 1 and o.block == 0 and o.team == 0
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -44,6 +45,10 @@ def test_opts_defaults():
     (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=5000), "copies"),
     (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=3, p=[1.0, 0.0, 2.0]), "Robin"),
     (dict(ne=(4, 4, 4), nparts=(2, 1, 1), copies=2, p=1.0, q=[0.0, -1.0]), "second-order"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), wave_rows=1), "wave_rows"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), block=256, wave_rows=2), "wave_rows"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), resident=3), "resident"),
+    (dict(ne=(4, 4, 4), nparts=(2, 1, 1), team=9), "team"),
 ])
 def test_invalid_arguments_rejected_on_the_host(kw, msg):
     with pytest.raises(sos.SosError) as ei:

@@ -51,8 +51,9 @@ __host__ __device__ inline int ra_waves(int nx, int ny, int cpt) {
   const int R = ra_rows(nx, cpt);
   return R < 1 ? 0 : (ny + R - 1) / R;
 }
-// LDS planes per march segment: the operand (two, alternating by step) and the
-// two y-pass results, each zero-padded by kPad.
+// LDS planes per march segment: the operand (a second one alternating by step
+// where second-order terms or wave-owned rows need it) and the two y-pass
+// results, each zero-padded by kPad; segments are kPlanes planes apart.
 constexpr int kPlanes = 4;
 // LDS planes a single-segment march uses: the second operand plane only with
 // second-order face terms or wave-owned rows.

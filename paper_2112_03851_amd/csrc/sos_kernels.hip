@@ -353,10 +353,18 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
   // first operand plane of the march: two below the segment, or (uniform z)
   // the subdomain's first plane when the segment starts there, since planes
   // outside the subdomain contribute nothing
+  // With uniform z the march also skips the halo plane that cannot reach an
+  // own plane: a mid plane (odd closure index) couples only to its two
+  // neighbouring planes, so below a mid first plane one halo plane suffices
+  // (the plane under it is a mid plane too and reaches no own plane), and
+  // likewise above a mid last plane. The skipped contributions are exact zeros.
+  auto is_mid = [&](int k) { return ((k + sl.zklo) & 1) != 0; };
   auto kfirst = [&](int m) {
-    if constexpr (ZU) return max(sl.uz0 - 2, 0);
+    if constexpr (ZU) return max(sl.uz0 - (is_mid(sl.uz0) ? 1 : 2), 0);
     else return sl.z0[m] - 2;
   };
+  // last operand plane the march needs (uniform z); later steps only drain
+  const int klast = ZU ? min(sl.uz1 - 1 + (is_mid(sl.uz1 - 1) ? 1 : 2), sl.nz - 1) : sl.nz - 1;
   T acc[CPT][5];
   T pr[CPT][3];
   // prefetch ring: slot q holds the operands of the step that is congruent to
@@ -393,7 +401,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       kp[m] = kfirst(m) + step;
-      inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] < sl.nz;
+      inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] <= klast;
       // make() runs on every step (on a clamped, valid plane outside the
       // subdomain, with own = false): its stores are off, its result unused
       const int kc = min(max(kp[m], 0), sl.nz - 1);
@@ -405,9 +413,9 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
       raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
     }
-    // uniform z: the steps past the subdomain's last plane only drain the
+    // uniform z: the steps past the last needed plane only drain the
     // accumulator ring and touch no LDS, so they skip both barriers
-    const bool sync = !ZU || kfirst(0) + step < sl.nz;
+    const bool sync = !ZU || kfirst(0) + step <= klast;
     if (sync) __syncthreads();
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {

@@ -759,7 +759,7 @@ int autotune(sos_ctx* c) {
       if (cd.res && !fused_args(c).res) continue;  // p and x do not fit in LDS with this team
       double ms_min = INFINITY;
       bool ok = true;
-      for (int rep = 0; rep < 2 && ok; ++rep) {
+      for (int rep = 0; rep < 3 && ok; ++rep) {  // fastest of three
         HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
         HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
                                team > 1 ? c->team_part : nullptr, st));

@@ -17,6 +17,7 @@ solves) on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -29,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "fused_cg_c2_pmc.json")
+PMC_GLOB = os.path.join(ROOT, "profiles", "fused_cg_*_pmc.json")
 GOLDEN_COUNTS = os.path.join(ROOT, "tests", "golden", "oracle_outer_counts.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2112_03851_amd", "csrc", "sos_kernels.hip")
 
@@ -44,22 +45,25 @@ def kernel_sha():
 METRIC = "Schwarz solves/s to 1e-8 rel residual + SpMV HBM GB/s (% peak), batched vs plain"
 
 
-def measured_traffic(launch_bytes, st):
+def measured_traffic(launch_bytes, st, workload_name):
     """HBM bytes per fused-kernel launch from committed rocprofv3 counters
     (FETCH_SIZE + WRITE_SIZE, each scaled by its reading for a plain copy),
-    if they were taken on the current kernel source with the same columns per
-    thread and team size;
+    if some counter file was taken on this workload and the current kernel
+    source with the same block shape, team size and residency level;
     per launch of this run (the counters' ratio to the algorithmic bytes)."""
-    try:
-        pmc = json.load(open(PMC_FILE))
-    except Exception:
-        return None
-    if pmc.get("kernel_sha") != kernel_sha():
-        return None
-    shape = (pmc.get("block"), pmc.get("cols_per_thread"), pmc.get("team"), pmc.get("wave_rows", 0))
-    if shape != (st["block"], st["cols_per_thread"], st["team"], st["wave_rows"]):
-        return None
-    return pmc["traffic_over_algorithmic"] * launch_bytes
+    shape = (st["block"], st["cols_per_thread"], st["team"], st["wave_rows"], st["resident"])
+    for path in sorted(glob.glob(PMC_GLOB)):
+        try:
+            pmc = json.load(open(path))
+        except Exception:
+            continue
+        if pmc.get("workload_name") != workload_name or pmc.get("kernel_sha") != kernel_sha():
+            continue
+        if (pmc.get("block"), pmc.get("cols_per_thread"), pmc.get("team"), pmc.get("wave_rows", 0),
+                pmc.get("resident")) != shape:
+            continue
+        return pmc["traffic_over_algorithmic"] * launch_bytes
+    return None
 
 
 def cpu_baseline(wl, budget_s, phi_gpu):
@@ -264,7 +268,7 @@ def main():
     launch_s = tot["kernel_ms"] * 1e-3 / tot["kernel_launches"]
     achieved = launch_bytes / launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes, st),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes, st, args.workload),
                 "kernel": "k_fused_cg<float>", "avg_launch_ms": launch_s * 1e3,
                 "algorithmic_bytes_per_launch": launch_bytes}
     batched = {"outer_iters": tot["outer_iters"] // args.steps, "inner_iters": tot["inner_iters"] // args.steps,

@@ -32,7 +32,7 @@ def _misfit_grad_gpu(prob, drho, idx, w, d, tol):
     obs = (phi[torch.tensor(idx, device="cuda")] * torch.tensor(w, device="cuda")).sum(dim=1)
     J = 0.5 * ((obs - torch.tensor(d, device="cuda")) ** 2).sum()
     J.backward()
-    return float(J), x.grad.cpu().numpy(), phi.detach().cpu().numpy()
+    return float(J.detach()), x.grad.cpu().numpy(), phi.detach().cpu().numpy()
 
 
 def test_adjoint_gradient_small_matches_direct_adjoint_and_fd():

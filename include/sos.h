@@ -46,7 +46,12 @@ enum {
   SOS_ENOMEM = -2,      /* device or host allocation failed                 */
   SOS_EHIP = -3,        /* a HIP runtime call failed                        */
   SOS_ENOCONV = -4,     /* max_outer reached; phi and stats still written   */
-  SOS_EBREAKDOWN = -5,  /* non-positive p'Ap or a non-finite value in a CG  */
+  SOS_EBREAKDOWN = -5,  /* an inner CG broke down: non-positive p'Ap, a
+                           non-finite value (e.g. NaN in the load), or a
+                           team member that gave up at the team barrier;
+                           detected at the next convergence check, after
+                           which the solve stops (stats are written, the
+                           broken subdomain keeps its iterate)            */
   SOS_ESTATE = -6       /* call out of order (e.g. no GPU, context unusable)*/
 };
 
@@ -155,10 +160,15 @@ typedef struct {
 /* Fill *opts with defaults for the given precision. */
 int sos_opts_default(sos_opts* opts, int32_t precision);
 
-/* Validate mesh/partition/Robin data, build subdomain and face descriptors,
- * allocate device workspaces on the current HIP device. Every subdomain's
- * x-y node plane ((2*ex+1)*(2*ey+1), ex, ey its element counts) must hold at
- * most 4096 nodes (SOS_EINVAL otherwise). */
+/* Set up the Robin-Schwarz method of Sec. 3 on a box partition: validate
+ * mesh/partition/Robin data (SOS_EINVAL: cuts not strictly increasing inside
+ * (0, ne), a zero-width subdomain, p <= 0, q < 0, all outer faces Neumann,
+ * bad options), build subdomain and directed-face descriptors (one Robin
+ * datum per directed interface face), allocate device workspaces on the
+ * current HIP device (SOS_ENOMEM), SOS_ESTATE without a usable device. Every
+ * subdomain's x-y node plane ((2*ex+1)*(2*ey+1), ex, ey its element counts)
+ * must hold at most 4096 nodes (SOS_EINVAL otherwise). *out is NULL on
+ * failure; on success the caller releases it with sos_destroy. */
 int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* robin,
               const sos_opts* opts, sos_ctx** out);
 
@@ -192,14 +202,19 @@ int sos_batch_rates(sos_ctx* ctx, const double* drho_elem, int32_t n_first, int3
                     double* rates, double* res_first, double* res_second, int32_t* best,
                     sos_stats* stats);
 
-/* Replace the Robin coefficients (same partition). */
+/* Replace the transmission coefficients of Sec. 3 (p, and q for order 2)
+ * on every directed face, keeping the partition and the load (SOS_EINVAL as
+ * in sos_setup; the context is unchanged on error). The outer state (u,
+ * lambda) is kept; a following solve starts from zero anyway. */
 int sos_set_robin(sos_ctx* ctx, const sos_robin* robin);
 
 /* Replace the run options (precision is fixed at setup). */
 int sos_set_opts(sos_ctx* ctx, const sos_opts* opts);
 
-/* Number of directed faces; if s_j_axis != NULL it receives 4 int32 per face:
- * s, j, axis, side (host memory, 4*n entries). */
+/* The directed interface faces (s <- j) of the partition, one Robin datum
+ * each (the many-subdomain reading of Sec. 3's two-subdomain exchange).
+ * *n receives their number; if s_j_axis != NULL it receives 4 int32 per face:
+ * s, j, axis, side (host memory, caller-owned, 4*n entries). */
 int sos_faces(const sos_ctx* ctx, int32_t* n, int32_t* s_j_axis_side);
 
 /* Layout of the concatenated subdomain vectors: n_sub; if offsets != NULL it
@@ -211,8 +226,11 @@ int sos_faces(const sos_ctx* ctx, int32_t* n, int32_t* s_j_axis_side);
 int sos_layout(const sos_ctx* ctx, int32_t* n_sub, int64_t* offsets, int32_t* dims,
                int32_t* lo, int64_t* face_off);
 
-/* Solve with the load of a per-element density anomaly drho (kg/m^3):
- * f_s = 4 pi G sum over s's own elements of drho_e int phi_i. Iterates until
+/* Solve the gravity equation of Sec. 2, Delta(Phi) = -4 pi G drho, with the
+ * Robin-Schwarz iteration of Sec. 3 (subdomain solves by diagonally
+ * preconditioned CG, Sec. 6) for a per-element density anomaly drho (kg/m^3,
+ * device, n_elem FP64): f_s = 4 pi G sum over s's own elements of
+ * drho_e int phi_i. Iterates until
  * the global relative residual ||f - K u~||/||f|| <= tol (checked every
  * check_every outer iterations; u~ the average of the subdomain copies) and
  * writes u~ to phi_nodes (0 on Dirichlet nodes). Starts from u = 0, lambda = 0.
@@ -223,9 +241,11 @@ int sos_layout(const sos_ctx* ctx, int32_t* n_sub, int64_t* offsets, int32_t* di
 int sos_solve(sos_ctx* ctx, const double* drho_elem, double tol, double* phi_nodes,
               sos_stats* stats);
 
-/* Same with a nodal load f (the weak right-hand side over all nodes; values on
- * Dirichlet nodes ignored), split among the subdomain copies of every node in
- * equal parts. */
+/* sos_solve for a nodal load f (Sec. 2's weak right-hand side over all
+ * nodes, device, FP64; values on Dirichlet nodes ignored), split among the
+ * subdomain copies of every node in equal parts (the same fixed point as the
+ * element-ownership split of sos_solve). Returns and errors as sos_solve;
+ * SOS_EINVAL on a context of several copies. */
 int sos_solve_load(sos_ctx* ctx, const double* f_nodes, double tol, double* phi_nodes,
                    sos_stats* stats);
 
@@ -272,6 +292,19 @@ int sos_set_density(sos_ctx* ctx, const double* drho_elem);
 int sos_iterate(sos_ctx* ctx, int32_t n, sos_stats* stats);
 /* Global relative residual and glued solution of the current state. */
 int sos_residual(sos_ctx* ctx, double* phi_nodes, double* rel_residual);
+/* Residual history (Sec. 6 stops on the global residual): the outer
+ * iteration count and relative residual of every convergence check since the
+ * last solve started (or sos_set_state); sos_iterate appends. *n receives the
+ * number of checks; the first min(cap, *n) are copied to outer / res (host
+ * memory, either may be NULL). SOS_LOG=1 in the environment also prints one
+ * line per check on stderr. */
+int sos_history(const sos_ctx* ctx, int32_t cap, int32_t* n, int32_t* outer, double* res);
+/* Failure-handling tests: spin_ticks bounds the team barrier's wait (wall
+ * clock ticks at 100 MHz; 0 restores the default, about 1.3 s); tag_skew = 1
+ * makes every member wait for a tag no member writes, so each team barrier
+ * ends at that bound and the solve reports SOS_EBREAKDOWN (every kernel still
+ * exits normally). tag_skew = 0 is normal operation. */
+int sos_debug_barrier(sos_ctx* ctx, int64_t spin_ticks, int32_t tag_skew);
 
 void sos_destroy(sos_ctx* ctx);
 const char* sos_last_error(void);

@@ -14,6 +14,8 @@
 
 #include <sys/stat.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/sos.h"
 #include "sos_internal.h"
 #include "sos_kernels.h"
@@ -80,7 +82,8 @@ struct sos_ctx {
   CgScal* scal = nullptr;
   int32_t* ndone = nullptr;
   unsigned long long* counters = nullptr;  // [0] inner iterations, [1] algorithmic bytes
-  double* h_res = nullptr;                 // pinned, coherent, device-mapped
+  int32_t* flags = nullptr;                // BreakBits of the current solve (device word)
+  double* h_res = nullptr;                 // pinned, coherent, device-mapped: [residual, flags]
   double* d_hres = nullptr;                // device view of h_res
   int32_t* h_ndone = nullptr;              // pinned
   unsigned long long* h_counters = nullptr;
@@ -104,6 +107,13 @@ struct sos_ctx {
   double kernel_ms = 0.0;
   int64_t kernel_launches = 0;
   bool have_load = false;
+  // team barrier wait bound and tag skew (sos_debug_barrier)
+  uint64_t spin_ticks = 1ull << 27;
+  int32_t tag_skew = 0;
+  // (outer iteration, relative residual) of every check since the last solve start
+  std::vector<int32_t> hist_outer;
+  std::vector<double> hist_res;
+  int32_t outer_total = 0;
 };
 
 namespace {
@@ -121,7 +131,7 @@ void release(sos_ctx* c) {
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_expairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_part,
-                  c->scal, c->ndone, c->counters};
+                  c->scal, c->ndone, c->counters, c->flags};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->h_res) hipHostFree(c->h_res);
@@ -482,7 +492,7 @@ int enqueue_check(sos_ctx* c, double* phi) {
   HIPCHK(launch_glue(c->dev, c->max_n, c->u, c->ut, st));
   HIPCHK(launch_local_residual(c->dev, c->seg.L, c->ut, c->f, c->rho, st));
   HIPCHK(launch_assemble_norm(c->dev, c->max_n, c->rho, c->f, c->ut, phi, c->part_norm, st));
-  HIPCHK(launch_final_norm(c->part_norm, c->n_norm_blocks, c->geo.copies, c->d_res, c->d_hres, st));
+  HIPCHK(launch_final_norm(c->part_norm, c->n_norm_blocks, c->geo.copies, c->flags, c->d_res, c->d_hres, st));
   return SOS_OK;
 }
 
@@ -512,6 +522,9 @@ FusedArgs fused_args(sos_ctx* c) {
   // resident p and x where they fit, else x alone, else neither
   a.res = 0;
   a.lds_bytes = (uint32_t)c->fused_lds;
+  a.flags = c->flags;
+  a.spin_ticks = c->spin_ticks;
+  a.tag_skew = c->tag_skew;
   if (c->fused_res && c->fp32 && a.zu) {
     for (int words = 2; words >= 1 && !a.res; --words) {
       const size_t total = std::max(fused_res_lds(c, words), c->fused_lds);
@@ -560,10 +573,11 @@ int stepwise_iteration(sos_ctx* c) {
     void* pold = (t & 1) ? c->p1 : c->p0;
     void* pnew = (t & 1) ? c->p0 : c->p1;
     HIPCHK(launch_cg_apply(c->dev, L, c->fp32, t, c->opts.max_inner, c->r, pold, pnew, c->q, c->part, c->scal,
-                           c->ndone, c->counters, st));
+                           c->ndone, c->counters, c->flags, st));
     ++launches;
     if (t == c->opts.max_inner) break;
-    HIPCHK(launch_cg_update(c->dev, L, c->fp32, t, c->x, pnew, c->r, c->q, c->part, c->scal, c->ndone, st));
+    HIPCHK(launch_cg_update(c->dev, L, c->fp32, t, c->x, pnew, c->r, c->q, c->part, c->scal, c->ndone, c->flags,
+                            st));
     ++launches;
     if ((t & 7) == 7) {
       HIPCHK(hipMemcpyAsync(c->h_ndone, c->ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -606,16 +620,47 @@ int build_graph(sos_ctx* c, int k) {
   return SOS_OK;
 }
 
+// Text of a BreakBits word.
+std::string break_text(int32_t bits) {
+  std::string t;
+  auto add = [&](int32_t b, const char* w) {
+    if (bits & b) t += (t.empty() ? "" : ", ") + std::string(w);
+  };
+  add(kBrkCurvature, "non-positive curvature p'Ap in a subdomain CG");
+  add(kBrkNonFinite, "non-finite value in a subdomain CG");
+  add(kBrkBarrier, "a team member gave up waiting at the team barrier");
+  add(kBrkLaunch, "launch shape does not fit the fused kernel variant");
+  return t;
+}
+
+// SOS_LOG=1 in the environment: one line per convergence check on stderr.
+bool log_checks() {
+  const char* v = getenv("SOS_LOG");
+  return v && *v && strcmp(v, "0") != 0;
+}
+
+void history_reset(sos_ctx* c) {
+  c->hist_outer.clear();
+  c->hist_res.clear();
+  c->outer_total = 0;
+}
+
 // Runs outer iterations until the residual <= tol (tol <= 0: exactly max_outer
-// iterations with one final check). Fills stats.
+// iterations with one check every check_every). Every check reads the global
+// residual and the solve's breakdown bits (one mapped host word each); a set
+// bit ends the run with SOS_EBREAKDOWN. Fills stats.
 int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* converged) {
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = c->stream;
   *c->h_counters = 0;
-  HIPCHK(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), st));  // never inside a graph
+  // cleared outside any graph (a captured memset node is avoided on purpose)
+  HIPCHK(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), st));
+  HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int32_t), st));
+  c->h_res[1] = 0.0;
   c->kernel_ms = 0.0;
   c->kernel_launches = 0;
   const bool batched = c->opts.mode == SOS_BATCHED;
+  const bool log = log_checks();
   // HIP events recorded inside a graph cannot be read back with
   // hipEventElapsedTime: timed runs launch eagerly; so do cooperative team
   // launches (not captured)
@@ -627,16 +672,23 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
   const bool graph = batched && c->opts.use_graph && !c->opts.timing && plain;
   const int every = c->opts.check_every;
   int done = 0, checks = 0;
+  int32_t brk = 0;
   double res = INFINITY, best = INFINITY;
   int best_at = 0;
   *converged = false;
   std::vector<hipEvent_t> evs;
+  char range[96];
   while (done < max_outer) {
     int k = std::min(every, max_outer - done);
+    snprintf(range, sizeof range, "sos outer %d-%d", c->outer_total + 1, c->outer_total + k);
+    roctxRangePushA(range);
     if (graph) {
       if (c->graph_k != k) {
         int rc = build_graph(c, k);
-        if (rc) return rc;
+        if (rc) {
+          roctxRangePop();
+          return rc;
+        }
       }
       HIPCHK(hipGraphLaunch(c->gexec, st));
     } else {
@@ -660,6 +712,7 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
       if (rc) return rc;
     }
     HIPCHK(hipStreamSynchronize(st));
+    roctxRangePop();
     if (c->opts.timing) {
       std::vector<hipEvent_t>& E = evs;
       for (size_t i = 0; i + 1 < E.size(); i += 2) {
@@ -672,9 +725,14 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
       evs.clear();
     }
     done += k;
+    c->outer_total += k;
     ++checks;
-    res = *c->h_res;
-    if (!std::isfinite(res)) break;
+    res = c->h_res[0];
+    brk = (int32_t)c->h_res[1];
+    c->hist_outer.push_back(c->outer_total);
+    c->hist_res.push_back(res);
+    if (log) fprintf(stderr, "sos: outer %d residual %.6e%s\n", c->outer_total, res, brk ? " (breakdown)" : "");
+    if (brk || !std::isfinite(res)) break;
     if (tol > 0.0 && res <= tol) {
       *converged = true;
       break;
@@ -706,6 +764,9 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
     stats->resident = fused_args(c).res;
     stats->team = c->fused_team;
   }
+  if (brk)
+    return fail(SOS_EBREAKDOWN, "inner solve breakdown after %d outer iterations: %s", c->outer_total,
+                break_text(brk).c_str());
   if (!std::isfinite(res)) return fail(SOS_EBREAKDOWN, "non-finite global residual");
   return SOS_OK;
 }
@@ -804,6 +865,7 @@ int solve_common(sos_ctx* c, double tol, double* phi, sos_stats* stats) {
   int rc = reset_state(c);
   if (rc) return rc;
   if (c->opts.mode == SOS_BATCHED && (rc = autotune(c))) return rc;
+  history_reset(c);
   bool conv = false;
   rc = run_outer(c, tol, c->opts.max_outer, stats, &conv);
   if (rc) return rc;
@@ -1055,18 +1117,20 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
       (rc = dalloc_v(&c->s1, c->n_local * es)) || (rc = dalloc(&c->part, 3 * c->seg.blocks.size())) ||
       (rc = dalloc(&c->part_norm, 2 * (size_t)c->n_norm_blocks)) || (rc = dalloc(&c->d_res, 4 + (size_t)copies)) ||
       (rc = dalloc(&c->scal, c->subs.size())) || (rc = dalloc(&c->ndone, 1)) || (rc = dalloc(&c->counters, 2)) ||
+      (rc = dalloc(&c->flags, 1)) ||
       (rc = dalloc(&c->team_part, c->subs.size() * kMaxTeam * 2 * 4))) {
     release(c);
     return rc;
   }
-  if (hipHostMalloc((void**)&c->h_res, sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+  if (hipHostMalloc((void**)&c->h_res, 2 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->d_hres, c->h_res, 0) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ndone, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_counters, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
     release(c);
     return fail(SOS_ENOMEM, "hipHostMalloc failed");
   }
-  *c->h_res = INFINITY;
+  c->h_res[0] = INFINITY;
+  c->h_res[1] = 0.0;
   if (opts->stream) {
     c->stream = (hipStream_t)opts->stream;
   } else {
@@ -1098,6 +1162,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   if (e == hipSuccess) e = hipMemset(c->lam, 0, std::max<int64_t>(1, c->n_lam) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->ut, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->rho, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->flags, 0, sizeof(int32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     release(c);
@@ -1203,6 +1268,7 @@ int sos_batch_rates(sos_ctx* c, const double* drho, int32_t n_first, int32_t n_s
   int rc = reset_state(c);
   if (rc) return rc;
   if (c->opts.mode == SOS_BATCHED && (rc = autotune(c))) return rc;
+  history_reset(c);
   bool conv = false;
   std::vector<double> r1(B), r2(B);
   sos_stats s1{}, s2{};
@@ -1281,7 +1347,7 @@ int sos_residual(sos_ctx* c, double* phi, double* res) {
   int rc = phi ? write_phi(c, phi) : enqueue_check(c, nullptr);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (res) *res = *c->h_res;
+  if (res) *res = c->h_res[0];
   return SOS_OK;
 }
 
@@ -1298,6 +1364,29 @@ int sos_set_state(sos_ctx* c, const double* u, const double* lam) {
   if (u) HIPCHK(hipMemcpyAsync(c->u, u, c->n_local * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (lam && c->n_lam) HIPCHK(hipMemcpyAsync(c->lam, lam, c->n_lam * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  history_reset(c);
+  return SOS_OK;
+}
+
+int sos_history(const sos_ctx* c, int32_t cap, int32_t* n, int32_t* outer, double* res) {
+  if (!c || !n) return fail(SOS_EINVAL, "NULL argument");
+  if (cap < 0) return fail(SOS_EINVAL, "cap must be >= 0");
+  *n = (int32_t)c->hist_res.size();
+  const size_t m = std::min<size_t>((size_t)cap, c->hist_res.size());
+  for (size_t i = 0; i < m; ++i) {
+    if (outer) outer[i] = c->hist_outer[i];
+    if (res) res[i] = c->hist_res[i];
+  }
+  return SOS_OK;
+}
+
+int sos_debug_barrier(sos_ctx* c, int64_t spin_ticks, int32_t tag_skew) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  if (spin_ticks < 0) return fail(SOS_EINVAL, "spin_ticks must be >= 0");
+  if (tag_skew != 0 && tag_skew != 1) return fail(SOS_EINVAL, "tag_skew must be 0 or 1");
+  c->spin_ticks = spin_ticks ? (uint64_t)spin_ticks : (1ull << 27);
+  c->tag_skew = tag_skew;
+  invalidate_graph(c);
   return SOS_OK;
 }
 

@@ -79,18 +79,29 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u,
                            const double* f, const double* lam, double* b, void* r_out, double* part,
                            double* team_part, hipStream_t st);
+// Why a subdomain's inner solve stopped early, OR-ed into one device word
+// per solve (the host reads it at every convergence check).
+enum BreakBits : int32_t {
+  kBrkCurvature = 1,   // non-positive p'Ap (or delta - beta gamma / alpha) in a CG
+  kBrkNonFinite = 2,   // a non-finite residual, dot product or step length
+  kBrkBarrier = 4,     // a team member gave up waiting at the team barrier
+  kBrkLaunch = 8,      // the launch does not fit the kernel variant (host error)
+};
+
 // Per-subdomain CG scalars from the residual partials (stepwise path).
 hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, double tol_rel,
                           double tol_abs, CgScal* scal, int32_t* ndone, hipStream_t st);
 // Stepwise CG, iteration t: p <- D^-1 r + beta p ; q = A p ; partial p'q.
 hipError_t launch_cg_apply(const Dev& d, const SegLaunch& L, int fp32, int t, int max_inner,
                            const void* r, const void* p_old, void* p_new, void* q, double* part,
-                           CgScal* scal, int32_t* ndone, unsigned long long* counters, hipStream_t st);
+                           CgScal* scal, int32_t* ndone, unsigned long long* counters, int32_t* flags,
+                           hipStream_t st);
 // Stepwise CG, iteration t: x += alpha p ; r -= alpha q ; partials r'z, r'r.
 hipError_t launch_cg_update(const Dev& d, const SegLaunch& L, int fp32, int t, void* x, const void* p,
                             void* r, const void* q, double* part, CgScal* scal, int32_t* ndone,
-                            hipStream_t st);
-// u += x for every subdomain whose inner solve took at least one iteration.
+                            int32_t* flags, hipStream_t st);
+// u += x for every subdomain whose inner solve took at least one iteration and
+// did not break down.
 hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, double* u, const void* x,
                                  const CgScal* scal, hipStream_t st);
 // The fused inner solve: one block per subdomain (order gives the block->subdomain
@@ -111,6 +122,10 @@ struct FusedArgs {
   int32_t rows;                     // wave-owned rows (see ra_rows): one barrier per plane
   int32_t res;                      // resident in LDS (FP32, uniform z only): 1 p and x, 2 x
   uint32_t lds_bytes;               // dynamic LDS of the launch (march planes + resident p, x)
+  int32_t* flags;                   // BreakBits of the solve, OR-ed by every block that stops early
+  uint64_t spin_ticks;              // team barrier: longest wait (wall clock ticks, 100 MHz)
+  int32_t tag_skew;                 // team barrier: 0; 1 waits for a tag no member writes, so
+                                    // every wait ends at spin_ticks (failure-handling tests)
 };
 // lds: the march planes; with a.res the launch takes a.lds_bytes (march planes
 // and the resident p and x of the largest z-range, at least lds). A team
@@ -152,9 +167,10 @@ hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, cons
 // Number of partials (pairs) written by launch_assemble_norm.
 int assemble_blocks(const Dev& d, int max_n);
 // Per copy res_c = sqrt(sum rr / sum ff) -> dev_out[3 + c]; the largest over
-// the copies -> dev_out[0] and host_out[0] (host-mapped, may be null).
-hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, double* dev_out, double* host_out,
-                             hipStream_t st);
+// the copies -> dev_out[0] and host_out[0] (host-mapped, may be null); the
+// solve's BreakBits (flags, may be null) -> host_out[1].
+hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, const int32_t* flags,
+                             double* dev_out, double* host_out, hipStream_t st);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st);
 // grad_e = 4 pi G sum_a psi_a int_e phi_a for every element (psi over all nodes).
 hipError_t launch_grad_density(const Geom& g, const double* psi, double G, double* grad, hipStream_t st);

@@ -1,751 +1,12 @@
-// HIP kernels of the Robin-Schwarz subdomain solves (gfx950, wave64).
-//
-// Operator. On a subdomain box the Robin-augmented Q2 stiffness is the
-// Kronecker sum of 1D factors (tensor-product elements, Sec. 3 operator p on
-// interface ends):
-//   A = Kx' (x) My (x) Mz + Mx (x) Ky' (x) Mz + Mx (x) My (x) Kz',
-// K' = K + diag(p at interface ends). It is applied matrix-free, marching over
-// the z-planes of the subdomain: every x-y plane of the input is staged in a
-// zero-padded LDS plane, reduced along y (u = My p, v = Ky' p) and then along x
-// (S = Kx' u + Mx v, T = Mx u), and each plane's (S, T) is scattered into a
-// ring of five z-accumulators held in registers:
-//   q_k = sum_k' Mz[k][k'] S_k' + Kz'[k][k'] T_k'.
-// About 30 flops per node, no MFMA: the path is bound by memory traffic.
-//
-// 1D rows of the assembled Q2 matrices on an interval of ne elements (closure
-// nodes 0..2ne): stiffness (1/(3h)) x {1,-8,14,-8,1} at interior vertices,
-// {-8,16,-8} at mid-points, {7,-8,1} / {1,-8,7} at the two ends; mass
-// (h/30) x {-1,2,8,2,-1}, {2,16,2}, {4,2,-1}, {-1,2,4}. The +-1 entries are
-// the same in every row, the +-2 entries are those of a vertex row or zero, so
-// only the centre entry depends on the node type. Neighbours outside the
-// subdomain's unknowns read the zero padding of the LDS plane (x, y) or feed
-// outputs outside the subdomain that are never stored (z).
-//
-// CG (Sec. 6: diagonal preconditioner). Each iteration is two passes:
-//   A: p = D^-1 r + beta p_old (recomputed on halo planes), q = A p, p'q
-//   B: x += alpha p, r -= alpha q, r'z, r'r  (pointwise)
-// Reductions are wave64 shuffles, then a fixed-order sum over waves and over
-// the blocks of a subdomain: results are bitwise repeatable.
-#include "sos_kernels.h"
-
-#include <math.h>
-
-#include <type_traits>
+// HIP kernels of the Robin-Schwarz subdomain solves (gfx950, wave64): the
+// outer-iteration kernels (exchange, glue, global residual, loads) and the
+// launchers. The kernel templates live in sos_device.h; the fused CG kernel's
+// launches are compiled per columns-per-thread value in sos_fused.hip.
+#include "sos_device.h"
 
 namespace sos {
 
-// Element li of an array whose base is uniform across the wavefront, addressed
-// with a 32-bit byte offset: the base stays in scalar registers and each lane
-// carries one 32-bit offset shared by all arrays indexed alike.
-template <typename T>
-__device__ __forceinline__ T& at(T* base, uint32_t li) {
-  using C = std::conditional_t<std::is_const<T>::value, const char, char>;
-  return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + li * (uint32_t)sizeof(T));
-}
-
-// Data that another workgroup of the same launch writes or reads (the halo
-// planes of a team of workgroups sharing one subdomain, the team's partial
-// sums) goes through agent-scope relaxed atomic loads and stores: they are
-// coherent across the L2 caches of all XCDs by themselves, so the team barrier
-// needs no L2 write-back or invalidation (which would also evict every other
-// vector of the sweep). Ordering comes from waiting for all stores before the
-// barrier arrival and from issuing these loads after it.
-template <typename T>
-__device__ __forceinline__ T ld_coh(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void st_coh(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// s_waitcnt vmcnt(0): every vector memory operation of the wave has completed
-__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
-
-// ---------------------------------------------------------------------------- 1D rows
-
-template <typename T>
-struct Row {
-  T k0, m0, k2, m2;  // centre and +-2 entries (the +-1 entries are -8ks, 2ms)
-};
-
-template <typename T>
-__device__ __forceinline__ Row<T> row_of(int c, int ne2, T ks, T ms, T elo, T ehi) {
-  Row<T> r;
-  if (c & 1) {
-    r.k0 = T(16) * ks;
-    r.m0 = T(16) * ms;
-    r.k2 = T(0);
-    r.m2 = T(0);
-  } else {
-    r.k2 = ks;
-    r.m2 = -ms;
-    if (c == 0) {
-      r.k0 = T(7) * ks + elo;
-      r.m0 = T(4) * ms;
-    } else if (c == ne2) {
-      r.k0 = T(7) * ks + ehi;
-      r.m0 = T(4) * ms;
-    } else {
-      r.k0 = T(14) * ks;
-      r.m0 = T(8) * ms;
-    }
-  }
-  return r;
-}
-
-// 0 mid-point, 1 interior vertex, 2 first closure node, 3 last closure node
-__device__ __forceinline__ int row_kind(int c, int ne2) {
-  return (c & 1) ? 0 : (c == 0 ? 2 : (c == ne2 ? 3 : 1));
-}
-
-// ---------------------------------------------------------------------------- reductions
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum N values over the block; every thread receives the sums (fixed order).
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N]) {
-  __shared__ double red[N * 16];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-  for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int n = 0; n < N; ++n) red[n * 16 + w] = v[n];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-    double s = 0.0;
-    for (int k = 0; k < nw; ++k) s += red[n * 16 + k];
-    v[n] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------- march geometry
-
-template <typename T, int CPT, bool Q = false>
-struct Slots {
-  int nx, ny, nz, S, PX, SP, G, seglen;
-  int64_t off;
-  int c[CPT], i[CPT], j[CPT], g[CPT], z0[CPT], z1[CPT], lp[CPT];
-  int uz0, uz1;  // the block's z-range (the segment of every slot when G == 1)
-  bool ra;       // wave-owned rows (G == 1): the x-pass needs no barrier
-  bool act[CPT];
-  T kx0[CPT], mx0[CPT], kx2[CPT], mx2[CPT];
-  T ky0[CPT], my0[CPT], ky2[CPT], my2[CPT];
-  T dv0[CPT], dv1[CPT], dv2[CPT], dv3[CPT];  // inverse diagonal per z row kind
-  T ex[CPT], ey[CPT], qx[CPT], qy[CPT];       // Robin p and q at the column's x / y interface end
-  T kx1, mx1, ky1, my1, kz1, mz1;
-  int zklo, zne2;
-  T zks, zms, zelo, zehi, zqlo, zqhi;
-  bool hasq;                                  // any second-order face term
-};
-
-template <typename T, int CPT, bool Q>
-__device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& d, const Geom& geo, int zb0,
-                                           int zb1, bool robin, bool ra = false) {
-  sl.nx = d.n[0];
-  sl.ny = d.n[1];
-  sl.nz = d.n[2];
-  sl.S = sl.nx * sl.ny;
-  sl.PX = sl.nx + 2 * kPad;
-  sl.SP = sl.PX * (sl.ny + 2 * kPad);
-  sl.off = d.off;
-  const int NT = blockDim.x;
-  const int zlen = zb1 - zb0;
-  // wave-owned rows: one segment, R rows per wave (the caller checks that the
-  // block's waves cover the plane)
-  sl.ra = ra;
-  sl.G = ra ? 1 : march_segments(sl.nx, sl.ny, zlen, NT, CPT);
-  const int R = ra ? ra_rows(sl.nx, CPT) : 0;
-  sl.uz0 = zb0;
-  sl.uz1 = zb1;
-  sl.seglen = (zlen + sl.G - 1) / sl.G;
-  const T ksx = T(geo.ks[0]), msx = T(geo.ms[0]);
-  const T ksy = T(geo.ks[1]), msy = T(geo.ms[1]);
-  sl.zks = T(geo.ks[2]);
-  sl.zms = T(geo.ms[2]);
-  sl.kx1 = T(-8) * ksx;
-  sl.mx1 = T(2) * msx;
-  sl.ky1 = T(-8) * ksy;
-  sl.my1 = T(2) * msy;
-  sl.kz1 = T(-8) * sl.zks;
-  sl.mz1 = T(2) * sl.zms;
-  sl.zklo = d.klo[2];
-  sl.zne2 = d.ne2[2];
-  sl.zelo = robin ? T(d.elo[2]) : T(0);
-  sl.zehi = robin ? T(d.ehi[2]) : T(0);
-  if constexpr (Q) {
-    sl.zqlo = robin ? T(d.qlo[2]) : T(0);
-    sl.zqhi = robin ? T(d.qhi[2]) : T(0);
-    sl.hasq = robin && (d.qlo[0] > 0.0 || d.qhi[0] > 0.0 || d.qlo[1] > 0.0 || d.qhi[1] > 0.0 ||
-                        d.qlo[2] > 0.0 || d.qhi[2] > 0.0);
-  } else {
-    sl.zqlo = sl.zqhi = T(0);
-    sl.hasq = false;
-  }
-  // centre entries of the four z row kinds (for the diagonal)
-  T kz0[4], mz0[4];
-  kz0[0] = T(16) * sl.zks;
-  mz0[0] = T(16) * sl.zms;
-  kz0[1] = T(14) * sl.zks;
-  mz0[1] = T(8) * sl.zms;
-  kz0[2] = T(7) * sl.zks + sl.zelo;
-  mz0[2] = T(4) * sl.zms;
-  kz0[3] = T(7) * sl.zks + sl.zehi;
-  mz0[3] = T(4) * sl.zms;
-#pragma unroll
-  for (int m = 0; m < CPT; ++m) {
-    int g, col;
-    bool cover;
-    if (ra) {
-      // slot q = lane + 64 m of wave w: row w R + q / nx, column q % nx; a
-      // slot past the wave's rows or the plane takes column 0 and stays idle
-      const int q = (threadIdx.x & 63) + 64 * m;
-      const int rq = q / sl.nx;
-      const int jr = (threadIdx.x >> 6) * R + rq;
-      cover = rq < R && jr < sl.ny;
-      g = 0;
-      col = cover ? (q - rq * sl.nx) + sl.nx * jr : 0;
-    } else {
-      const int sigma = threadIdx.x + NT * m;
-      g = sigma / sl.S;
-      col = sigma - g * sl.S;
-      cover = g < sl.G;
-    }
-    sl.g[m] = g;
-    sl.z0[m] = zb0 + g * sl.seglen;
-    sl.z1[m] = min(zb1, sl.z0[m] + sl.seglen);
-    sl.act[m] = cover && (sl.z0[m] < zb1);
-    sl.c[m] = col;
-    const int i = col % sl.nx, j = col / sl.nx;
-    sl.i[m] = i;
-    sl.j[m] = j;
-    sl.lp[m] = g * kPlanes * sl.SP + (i + kPad) + sl.PX * (j + kPad);
-    Row<T> rx = row_of<T>(i + d.klo[0], d.ne2[0], ksx, msx, robin ? T(d.elo[0]) : T(0),
-                          robin ? T(d.ehi[0]) : T(0));
-    Row<T> ry = row_of<T>(j + d.klo[1], d.ne2[1], ksy, msy, robin ? T(d.elo[1]) : T(0),
-                          robin ? T(d.ehi[1]) : T(0));
-    sl.kx0[m] = rx.k0;
-    sl.mx0[m] = rx.m0;
-    sl.kx2[m] = rx.k2;
-    sl.mx2[m] = rx.m2;
-    sl.ky0[m] = ry.k0;
-    sl.my0[m] = ry.m0;
-    sl.ky2[m] = ry.k2;
-    sl.my2[m] = ry.m2;
-    // interface-end coefficients of this column (0/1 blends, no selects
-    // between descriptor fields)
-    const int cxi = i + d.klo[0], cyj = j + d.klo[1];
-    const T wxl = cxi == 0 ? T(1) : T(0), wxh = cxi == d.ne2[0] ? T(1) : T(0);
-    const T wyl = cyj == 0 ? T(1) : T(0), wyh = cyj == d.ne2[1] ? T(1) : T(0);
-    const T rb = robin ? T(1) : T(0);
-    const T a1 = rx.k0 * ry.m0 + rx.m0 * ry.k0;
-    const T a2 = rx.m0 * ry.m0;
-    T b1 = T(0), b2 = T(0), b3 = T(0);
-    if constexpr (Q) {
-      sl.ex[m] = rb * (wxl * T(d.elo[0]) + wxh * T(d.ehi[0]));
-      sl.ey[m] = rb * (wyl * T(d.elo[1]) + wyh * T(d.ehi[1]));
-      sl.qx[m] = rb * (wxl * T(d.qlo[0]) + wxh * T(d.qhi[0]));
-      sl.qy[m] = rb * (wyl * T(d.qlo[1]) + wyh * T(d.qhi[1]));
-      // second-order face terms on the diagonal (plain 1D centres, no Robin p)
-      const T kxp = rx.k0 - sl.ex[m], kyp = ry.k0 - sl.ey[m];
-      b1 = sl.qx[m] * kyp + sl.qy[m] * kxp;      // times mz0
-      b2 = sl.qx[m] * ry.m0 + sl.qy[m] * rx.m0;  // times plain kz0
-      b3 = kxp * ry.m0 + rx.m0 * kyp;            // times q_z at a z end
-    } else {
-      (void)wxl; (void)wxh; (void)wyl; (void)wyh; (void)rb;
-    }
-    const T kzp0 = T(16) * sl.zks, kzp1 = T(14) * sl.zks, kzp2 = T(7) * sl.zks, kzp3 = T(7) * sl.zks;
-    sl.dv0[m] = T(1) / (a1 * mz0[0] + a2 * kz0[0] + b1 * mz0[0] + b2 * kzp0);
-    sl.dv1[m] = T(1) / (a1 * mz0[1] + a2 * kz0[1] + b1 * mz0[1] + b2 * kzp1);
-    sl.dv2[m] = T(1) / (a1 * mz0[2] + a2 * kz0[2] + b1 * mz0[2] + b2 * kzp2 + sl.zqlo * b3);
-    sl.dv3[m] = T(1) / (a1 * mz0[3] + a2 * kz0[3] + b1 * mz0[3] + b2 * kzp3 + sl.zqhi * b3);
-  }
-}
-
-template <typename T, int CPT, bool Q>
-__device__ __forceinline__ T slot_dinv(const Slots<T, CPT, Q>& sl, int m, int k) {
-  // blend with 0/1 weights: a select between struct fields would make the
-  // compiler keep the whole slot state in scratch memory
-  const int c = k + sl.zklo;
-  const bool mid = (c & 1) != 0;
-  const T w0 = mid ? T(1) : T(0);
-  const T w2 = (!mid && c == 0) ? T(1) : T(0);
-  const T w3 = (!mid && c == sl.zne2) ? T(1) : T(0);
-  const T w1 = T(1) - w0 - w2 - w3;
-  return w0 * sl.dv0[m] + w1 * sl.dv1[m] + w2 * sl.dv2[m] + w3 * sl.dv3[m];
-}
-
-template <typename T>
-__device__ __forceinline__ void lds_zero(T* lds, int n) {
-  for (int e = threadIdx.x; e < n; e += blockDim.x) lds[e] = T(0);
-}
-
-// The z-march, software-pipelined: fetch(li) issues the global loads of the
-// operand at local index li = c + S k of the subdomain (always a valid node)
-// kPrefetch planes ahead of its use; make(raw, li, own, dinv) turns them into
-// the operand
-// (own: the plane belongs to the slot's segment; dinv: inverse diagonal).
-// store(li, en, i, j, k, q, p_k, dinv) receives the finished output at plane k
-// of the slot's own segment, with the operand value p_k at that node (or the
-// value make() carried for it), when en; make() and store() are called on every
-// step and write nothing when own / en is false. Functors index pointers
-// already offset to the subdomain (uniform base + 32-bit index).
-constexpr int kPrefetch = 3;
-
-// make() returns the operand of the stencil, or an operand with a separate
-// value carried to store() (default: the operand itself).
-template <typename T>
-struct OpCarry {
-  T op, carry;
-};
-template <typename T>
-__device__ __forceinline__ T op_of(T v) { return v; }
-template <typename T>
-__device__ __forceinline__ T op_of(const OpCarry<T>& v) { return v.op; }
-template <typename T>
-__device__ __forceinline__ T carry_of(T v) { return v; }
-template <typename T>
-__device__ __forceinline__ T carry_of(const OpCarry<T>& v) { return v.carry; }
-
-// ZU: the block marches one segment (G == 1), so every plane index is uniform
-// across the block and the z-dependent row coefficients, the diagonal's
-// z-kind and the plane tests run on the scalar unit.
-template <bool ZU = false, typename T, int CPT, bool Q, class FetchF, class MakeF, class StoreF>
-__device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, FetchF& fetch, MakeF& make,
-                                       StoreF& store) {
-  auto zlo = [&](int m) {
-    if constexpr (ZU) return sl.uz0;
-    else return sl.z0[m];
-  };
-  auto zhi = [&](int m) {
-    if constexpr (ZU) return sl.uz1;
-    else return sl.z1[m];
-  };
-  using Raw = decltype(fetch(uint32_t(0), false));
-  // coh: the plane lies outside the block's own z-range (another block of a
-  // team writes it); edge: an own plane within two of the range's ends (the
-  // neighbouring team members read it)
-  auto coh_of = [&](int k) { return k < sl.uz0 || k >= sl.uz1; };
-  // inverse diagonal at plane k; with uniform z the row kind is uniform and a
-  // select chain on a scalar condition replaces the 0/1 blend
-  auto dinv_of = [&](int m, int k) {
-    if constexpr (ZU) {
-      const int c = k + sl.zklo;
-      const T d0 = sl.dv0[m], d1 = sl.dv1[m], d2 = sl.dv2[m], d3 = sl.dv3[m];
-      T dv = (c & 1) != 0 ? d0 : d1;
-      dv = c == 0 ? d2 : dv;
-      dv = c == sl.zne2 ? d3 : dv;
-      return dv;
-    } else {
-      return slot_dinv(sl, m, k);
-    }
-  };
-  auto edge_of = [&](int k) { return k < sl.uz0 + 2 || k >= sl.uz1 - 2; };
-  // first operand plane of the march: two below the segment, or (uniform z)
-  // the subdomain's first plane when the segment starts there, since planes
-  // outside the subdomain contribute nothing
-  // With uniform z the march also skips the halo plane that cannot reach an
-  // own plane: a mid plane (odd closure index) couples only to its two
-  // neighbouring planes, so below a mid first plane one halo plane suffices
-  // (the plane under it is a mid plane too and reaches no own plane), and
-  // likewise above a mid last plane. The skipped contributions are exact zeros.
-  auto is_mid = [&](int k) { return ((k + sl.zklo) & 1) != 0; };
-  auto kfirst = [&](int m) {
-    if constexpr (ZU) return max(sl.uz0 - (is_mid(sl.uz0) ? 1 : 2), 0);
-    else return sl.z0[m] - 2;
-  };
-  // last operand plane the march needs (uniform z); later steps only drain
-  const int klast = ZU ? min(sl.uz1 - 1 + (is_mid(sl.uz1 - 1) ? 1 : 2), sl.nz - 1) : sl.nz - 1;
-  T acc[CPT][5];
-  T pr[CPT][3];
-  // prefetch ring: slot q holds the operands of the step that is congruent to
-  // q modulo kPrefetch. The step loop is unrolled kPrefetch times so every
-  // slot is a fixed set of registers: a register receiving a load in flight is
-  // never copied, so each use waits only for its own load.
-  Raw raw[CPT][kPrefetch];
-#pragma unroll
-  for (int m = 0; m < CPT; ++m) {
-#pragma unroll
-    for (int q = 0; q < 5; ++q) acc[m][q] = T(0);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) pr[m][q] = T(0);
-#pragma unroll
-    for (int q = 0; q < kPrefetch; ++q) {
-      // unconditional load from a clamped, always valid plane: a fixed number
-      // of loads per step lets every use wait for its own load only
-      const int kq = min(max(kfirst(m) + q, 0), sl.nz - 1);
-      raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
-    }
-  }
-  // the output of plane k is complete two steps after operand plane k + 2
-  const int steps = ZU ? sl.uz1 + 2 - kfirst(0) : sl.seglen + 4;
-  const int PX = sl.PX, SP = sl.SP;
-  auto one_step = [&](auto ucst, int step) {
-    constexpr int U = decltype(ucst)::value;
-    // with second-order terms (the x-pass reads the operand plane) or
-    // wave-owned rows (no barrier after the y-pass) the operand plane
-    // alternates between two LDS planes, so the next step's writes never meet
-    // this step's reads; otherwise the barrier after the y-pass orders them
-    const int po = ((Q || sl.ra) && (step & 1)) ? 3 * SP : 0;
-    bool inr[CPT];
-    int kp[CPT];
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      kp[m] = kfirst(m) + step;
-      inr[m] = sl.act[m] && kp[m] >= 0 && kp[m] <= klast;
-      // make() runs on every step (on a clamped, valid plane outside the
-      // subdomain, with own = false): its stores are off, its result unused
-      const int kc = min(max(kp[m], 0), sl.nz - 1);
-      const bool own = sl.act[m] && kp[m] >= zlo(m) && kp[m] < zhi(m);
-      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, edge_of(kc), dinv_of(m, kc));
-      if (inr[m]) lds[sl.lp[m] + po] = T(op_of(mv));
-      // a plane outside the subdomain is never stored, so its carry is unused
-      pr[m][2] = T(carry_of(mv));
-      const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
-      raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
-    }
-    // uniform z: the steps past the last needed plane only drain the
-    // accumulator ring and touch no LDS, so they skip both barriers
-    const bool sync = !ZU || kfirst(0) + step <= klast;
-    if (sync) __syncthreads();
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      if (inr[m]) {
-        const T* P = lds + sl.lp[m] + po;
-        const T a0 = P[0];
-        const T s1 = P[-PX] + P[PX];
-        const T s2 = P[-2 * PX] + P[2 * PX];
-        const T u = sl.my0[m] * a0 + sl.my1 * s1 + sl.my2[m] * s2;
-        const T v = sl.ky0[m] * a0 + sl.ky1 * s1 + sl.ky2[m] * s2;
-        lds[sl.lp[m] + SP] = u;
-        lds[sl.lp[m] + 2 * SP] = v;
-      }
-    }
-    // wave-owned rows: the x-pass reads the y-pass results of its own wave
-    // (LDS operations of a wave complete in order), and the next step's y-pass
-    // rewrites them only after this wave's x-pass
-    if (sync && !sl.ra) __syncthreads();
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      if (inr[m]) {
-        const T* U_ = lds + sl.lp[m] + SP;
-        const T* V = U_ + SP;
-        const T u0 = U_[0], u1 = U_[-1] + U_[1], u2 = U_[-2] + U_[2];
-        const T v0 = V[0], v1 = V[-1] + V[1], v2 = V[-2] + V[2];
-        T Sx = sl.kx0[m] * u0 + sl.kx1 * u1 + sl.kx2[m] * u2 + sl.mx0[m] * v0 + sl.mx1 * v1 + sl.mx2[m] * v2;
-        T Tx = sl.mx0[m] * u0 + sl.mx1 * u1 + sl.mx2[m] * u2;
-        T zc = T(0);  // second-order z-face term of the centre row
-        if constexpr (Q) if (sl.hasq) {
-          // second-order faces q (tangential stiffness with plain 1D factors):
-          // an x-face adds q (Ky (x) Mz + My (x) Kz) on its plane, a y-face
-          // q (Kx (x) Mz + Mx (x) Kz), a z-face q (Kx (x) My + Mx (x) Ky)
-          const T* P = lds + sl.lp[m] + po;
-          const T p0 = P[0], p1 = P[-1] + P[1], p2 = P[-2] + P[2];
-          const T pm = sl.mx0[m] * p0 + sl.mx1 * p1 + sl.mx2[m] * p2;
-          const T pk = (sl.kx0[m] - sl.ex[m]) * p0 + sl.kx1 * p1 + sl.kx2[m] * p2;
-          const T sf = sl.qx[m] * (v0 - sl.ey[m] * p0) + sl.qy[m] * pk;
-          const T tf = sl.qx[m] * u0 + sl.qy[m] * pm;
-          const int cz = kp[m] + sl.zklo;
-          const T wzl = cz == 0 ? T(1) : T(0), wzh = cz == sl.zne2 ? T(1) : T(0);
-          const T zq = wzl * sl.zqlo + wzh * sl.zqhi;
-          const T ez = wzl * sl.zelo + wzh * sl.zehi;
-          zc = zq * (Sx - sl.ex[m] * u0 - sl.ey[m] * pm) - ez * tf;
-          Sx += sf;
-          Tx += tf;
-        }
-        const Row<T> rz = row_of<T>(kp[m] + sl.zklo, sl.zne2, sl.zks, sl.zms, sl.zelo, sl.zehi);
-        const T c1 = sl.mz1 * Sx + sl.kz1 * Tx;
-        const T c2 = rz.m2 * Sx + rz.k2 * Tx;
-        acc[m][0] += c2;
-        acc[m][1] += c1;
-        if constexpr (Q) acc[m][2] += rz.m0 * Sx + rz.k0 * Tx + zc;
-        else acc[m][2] += rz.m0 * Sx + rz.k0 * Tx;
-        acc[m][3] += c1;
-        acc[m][4] = c2;
-      } else {
-        acc[m][4] = T(0);
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      {
-        const int k = kp[m] - 2;
-        const bool en = sl.act[m] && k >= zlo(m) && k < zhi(m);
-        const int kc = min(max(k, 0), sl.nz - 1);
-        store(uint32_t(sl.c[m] + sl.S * kc), en, edge_of(kc), sl.i[m], sl.j[m], kc, acc[m][0], pr[m][0],
-              dinv_of(m, kc));
-      }
-      acc[m][0] = acc[m][1];
-      acc[m][1] = acc[m][2];
-      acc[m][2] = acc[m][3];
-      acc[m][3] = acc[m][4];
-      pr[m][0] = pr[m][1];
-      pr[m][1] = pr[m][2];
-    }
-  };
-  static_assert(kPrefetch == 3, "the step loop below is unrolled for a ring of three");
-  int step = 0;
-  for (; step + 3 <= steps; step += 3) {
-    one_step(std::integral_constant<int, 0>(), step);
-    one_step(std::integral_constant<int, 1>(), step + 1);
-    one_step(std::integral_constant<int, 2>(), step + 2);
-  }
-  if (step < steps) one_step(std::integral_constant<int, 0>(), step++);
-  if (step < steps) one_step(std::integral_constant<int, 1>(), step++);
-}
-
-template <typename T>
-struct Pair {
-  T a, b;
-};
-
-// Launch bound per x-y columns per thread (the host never launches more).
-template <int CPT>
-// Two columns per thread: up to 11 waves (3 per SIMD, 168 VGPRs); three: up to
-// 8 waves (2 per SIMD, 256 VGPRs). A block a few waves larger than the plane
-// needs spreads the second (third) column of the threads over more waves, so
-// no SIMD carries more of them than the others.
-struct Bound {
-  static constexpr int value = CPT == 2 ? 704 : (CPT == 3 ? 512 : 1024);
-};
-
 int launch_bound(int cpt) { return cpt == 2 ? 704 : (cpt == 3 ? 512 : 1024); }
-
-// Robin data added to the local right-hand side at node (i, j, k).
-struct LamOff {
-  int64_t o[6];  // lambda offset per (axis, side) face, -1 if none
-};
-
-__device__ __forceinline__ LamOff lam_offsets(const Dev& d, const SubDesc& sd) {
-  LamOff L;
-#pragma unroll
-  for (int f = 0; f < 6; ++f) L.o[f] = sd.face[f] >= 0 ? d.faces[sd.face[f]].lam_off : -1;
-  return L;
-}
-
-__device__ __forceinline__ double lam_terms(const LamOff& L, const double* lam, int i, int j, int k, int nx,
-                                            int ny, int nz) {
-  double a = 0.0;
-  if (i == 0 && L.o[0] >= 0) a += lam[L.o[0] + j + (int64_t)ny * k];
-  if (i == nx - 1 && L.o[1] >= 0) a += lam[L.o[1] + j + (int64_t)ny * k];
-  if (j == 0 && L.o[2] >= 0) a += lam[L.o[2] + i + (int64_t)nx * k];
-  if (j == ny - 1 && L.o[3] >= 0) a += lam[L.o[3] + i + (int64_t)nx * k];
-  if (k == 0 && L.o[4] >= 0) a += lam[L.o[4] + i + (int64_t)nx * j];
-  if (k == nz - 1 && L.o[5] >= 0) a += lam[L.o[5] + i + (int64_t)nx * j];
-  return a;
-}
-
-// Algorithmic bytes of an inner solve of t CG iterations on subdomain sd:
-// per iteration pass A reads r, p_old and writes p, q, pass B reads p, q, x, r
-// and writes x, r (10 vectors; the first iteration reads neither p_old nor x),
-// then the correction u += x reads x and u and writes u (FP64).
-__device__ __forceinline__ unsigned long long cg_bytes(const SubDesc& sd, int t, int es) {
-  if (t <= 0) return 0ull;
-  const unsigned long long n = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
-  return n * ((unsigned long long)(10 * t - 2) * es + es + 16ull);
-}
-
-// Algorithmic bytes of a fused inner solve of t >= 1 iterations: a
-// preconditioned CG iteration with its dot products fused into the operator
-// sweep moves 12 words per unknown (apply: read p, write q; updates of x, r, p
-// and z = D^-1 r: 7; dots: 3), whatever the kernel keeps on chip; then
-// u += x reads x and reads and writes u in FP64.
-__device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int t, int es) {
-  if (t <= 0) return 0ull;
-  const unsigned long long n = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
-  return n * ((unsigned long long)(12 * t) * es + es + 16ull);
-}
-
-// ---------------------------------------------------------------------------- outer kernels
-
-// b = f + sum_j R_sj^T lambda_{s<-j} on the boundary-shell nodes of planes
-// [z0, z1) of subdomain sd (off the shell b = f is left as it is): the z-face
-// planes whole, the other planes' perimeters; every node is written by the
-// block that owns its plane.
-__device__ __forceinline__ void shell_rhs(const Dev& d, const SubDesc& sd, int z0, int z1,
-                                          const double* __restrict__ f, const double* __restrict__ lam,
-                                          double* __restrict__ b) {
-  const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2], S = nx * ny;
-  const int xs = nx > 1 ? 2 : 1, ys = ny > 1 ? 2 : 1, ix = max(nx - 2, 0);
-  const int perim = xs * ny + ys * ix;
-  const int nzf = (z0 == 0 ? 1 : 0) + (z1 == nz && nz - 1 != 0 ? 1 : 0);  // z-face planes in range
-  const int k0 = z0 == 0 ? 1 : z0, k1 = z1 == nz ? nz - 1 : z1;            // perimeter-only planes
-  const int n_face = nzf * S, total = n_face + max(k1 - k0, 0) * perim;
-  const LamOff L = lam_offsets(d, sd);
-#pragma unroll 4
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    int i, j, k;
-    if (t < n_face) {
-      k = (t < S && z0 == 0) ? 0 : nz - 1;
-      const int e = t % S;
-      i = e % nx;
-      j = e / nx;
-    } else {
-      const int q = (t - n_face) / perim, e = (t - n_face) - q * perim;
-      k = k0 + q;
-      if (e < xs * ny) {
-        i = e < ny ? 0 : nx - 1;
-        j = e < ny ? e : e - ny;
-      } else {
-        const int e2 = e - xs * ny;
-        j = e2 < ix ? 0 : ny - 1;
-        i = 1 + (e2 < ix ? e2 : e2 - ix);
-      }
-    }
-    const int64_t idx = sd.off + i + (int64_t)nx * (j + (int64_t)ny * k);
-    b[idx] = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
-  }
-}
-
-// r = b - A u with b = f + sum_j R_sj^T lambda_{s<-j}: each block first
-// rewrites b on the shell nodes of its own planes (the march uses b only
-// there, and at its own interior nodes b = f is kept); RZ: also r'D^-1 r (the
-// stepwise CG's first gamma). ZU: every block marches one segment (the host
-// checks; otherwise the partials are NaN and the solve reports a breakdown).
-template <typename TO, int CPT, bool Q, bool RZ, bool ZU = false>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
-                                                   const double* __restrict__ f, const double* __restrict__ lam,
-                                                   double* __restrict__ b, TO* __restrict__ r,
-                                                   double* __restrict__ part, double* __restrict__ team_part) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* lds = reinterpret_cast<double*>(smem);
-  // the fused kernel that follows tags its team partials from epoch 0: clear
-  // every slot (tag 0)
-  if (team_part && blockIdx.x == 0)
-    for (int i = threadIdx.x; i < d.geo.n_sub * kMaxTeam * 2 * 4; i += blockDim.x) team_part[i] = 0.0;
-  const BlockDesc bd = blocks[blockIdx.x];
-  const SubDesc sd = d.subs[bd.s];
-  shell_rhs(d, sd, bd.z0, bd.z1, f, lam, b);
-  Slots<double, CPT, Q> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  lds_zero(lds, sl.G * kPlanes * sl.SP);
-  // the block's b writes are visible to its own march after the barrier
-  __syncthreads();
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  const bool bad = ZU && sl.G != 1;
-  const double* __restrict__ ub = u + sl.off;
-  const double* __restrict__ bb = b + sl.off;
-  TO* __restrict__ rb = r + sl.off;
-  auto fetch = [=](uint32_t li, bool) { return Pair<double>{at(ub, li), at(bb, li)}; };
-  auto make = [](const Pair<double>& v, uint32_t, bool, bool, double) { return OpCarry<double>{v.a, v.b}; };
-  auto store = [&](uint32_t li, bool en, bool, int, int, int, double q, double bv, double dinv) {
-    if (!en) return;
-    const TO rt = TO(bv - q);
-    at(rb, li) = rt;
-    const double rd = double(rt);
-    if constexpr (RZ) a0 += rd * rd * dinv;
-    else (void)dinv;
-    a1 += rd * rd;
-    a2 += bv * bv;
-  };
-  if (!bad) zmarch<ZU>(sl, lds, fetch, make, store);
-  double acc[3] = {a0, a1, a2};
-  block_sum(acc);
-  if (bad) acc[0] = acc[1] = acc[2] = __builtin_nan("");
-  if (threadIdx.x == 0) {
-    part[3 * blockIdx.x + 0] = acc[0];
-    part[3 * blockIdx.x + 1] = acc[1];
-    part[3 * blockIdx.x + 2] = acc[2];
-  }
-}
-
-// rho = f - K^N ut (Neumann local stiffness: no Robin terms).
-template <int CPT>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ ut,
-                                                         const double* __restrict__ f, double* __restrict__ rho) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* lds = reinterpret_cast<double*>(smem);
-  const BlockDesc bd = blocks[blockIdx.x];
-  const SubDesc sd = d.subs[bd.s];
-  Slots<double, CPT, false> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
-  lds_zero(lds, sl.G * kPlanes * sl.SP);
-  __syncthreads();
-  const double* __restrict__ utb = ut + sl.off;
-  const double* __restrict__ fb = f + sl.off;
-  double* __restrict__ rhob = rho + sl.off;
-  auto fetch = [=](uint32_t li, bool) { return at(utb, li); };
-  auto make = [](double v, uint32_t, bool, bool, double) { return v; };
-  auto store = [=](uint32_t li, bool en, bool, int, int, int, double q, double, double) {
-    if (en) at(rhob, li) = at(fb, li) - q;
-  };
-  zmarch(sl, lds, fetch, make, store);
-}
-
-// y = A x (diagnostic).
-template <typename T, int CPT, bool Q>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_apply(Dev d, const BlockDesc* blocks, const T* __restrict__ x,
-                                                T* __restrict__ y) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* lds = reinterpret_cast<T*>(smem);
-  const BlockDesc bd = blocks[blockIdx.x];
-  const SubDesc sd = d.subs[bd.s];
-  Slots<T, CPT, Q> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  lds_zero(lds, sl.G * kPlanes * sl.SP);
-  __syncthreads();
-  const T* __restrict__ xb = x + sl.off;
-  T* __restrict__ yb = y + sl.off;
-  auto fetch = [=](uint32_t li, bool) { return at(xb, li); };
-  auto make = [](T v, uint32_t, bool, bool, T) { return v; };
-  auto store = [=](uint32_t li, bool en, bool, int, int, int, T q, T, T) {
-    if (en) at(yb, li) = q;
-  };
-  zmarch(sl, lds, fetch, make, store);
-}
-
-// Pass B of a CG iteration over the slot's planes [z0, z1): x += alpha p,
-// r -= alpha q, accumulating r'D^-1 r and r'r. Four planes per round so that
-// sixteen loads are in flight before the first use.
-template <typename T, int CPT, bool Q>
-__device__ __forceinline__ void cg_pass_b(const Slots<T, CPT, Q>& sl, bool first, T alpha, T* __restrict__ x,
-                                          const T* __restrict__ p, T* __restrict__ r, const T* __restrict__ q,
-                                          double& arz, double& arr) {
-  T* __restrict__ xb = x + sl.off;
-  const T* __restrict__ pb = p + sl.off;
-  T* __restrict__ rb = r + sl.off;
-  const T* __restrict__ qb = q + sl.off;
-#pragma unroll
-  for (int m = 0; m < CPT; ++m) {
-    if (!sl.act[m]) continue;
-    for (int k = sl.z0[m]; k < sl.z1[m]; k += 4) {
-      T pv[4], xv[4], rv[4], qv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int kk = k + u;
-        if (kk < sl.z1[m]) {
-          const uint32_t li = sl.c[m] + sl.S * kk;
-          pv[u] = at(pb, li);
-          xv[u] = first ? T(0) : at(xb, li);
-          rv[u] = at(rb, li);
-          qv[u] = at(qb, li);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int kk = k + u;
-        if (kk < sl.z1[m]) {
-          const uint32_t li = sl.c[m] + sl.S * kk;
-          at(xb, li) = xv[u] + alpha * pv[u];
-          const T rn = rv[u] - alpha * qv[u];
-          at(rb, li) = rn;
-          const double rd = double(rn);
-          arz += rd * rd * double(slot_dinv(sl, m, kk));
-          arr += rd * rd;
-        }
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------- stepwise CG
 
@@ -770,490 +31,6 @@ __global__ void k_cg_init(int n_sub, const int32_t* __restrict__ bfirst, const d
   c.breakdown = 0;
   c.pad = 0;
   scal[s] = c;
-}
-
-template <typename T, int CPT, bool Q>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
-                                                   int t, int max_inner, const T* __restrict__ r,
-                                                   const T* __restrict__ pold, T* __restrict__ pnew,
-                                                   T* __restrict__ q, double* __restrict__ part,
-                                                   CgScal* __restrict__ scal, int32_t* ndone,
-                                                   unsigned long long* counters) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* lds = reinterpret_cast<T*>(smem);
-  const BlockDesc bd = blocks[blockIdx.x];
-  const int s = bd.s;
-  if (scal[s].done) return;
-  const int b0 = bfirst[s], b1 = bfirst[s + 1];
-  const bool leader = (blockIdx.x == b0) && (threadIdx.x == 0);
-  double rz, rr;
-  if (t == 0) {
-    rz = scal[s].rz[0];
-    rr = scal[s].rr0;
-  } else {
-    rz = 0.0;
-    rr = 0.0;
-    for (int b = b0; b < b1; ++b) {
-      rz += part[3 * b + 1];
-      rr += part[3 * b + 2];
-    }
-  }
-  const bool bad = !isfinite(rr) || !isfinite(rz);
-  if (bad || !(rr > scal[s].stop2) || t >= max_inner) {
-    if (leader) {
-      scal[s].done = 1;
-      scal[s].iters = t;
-      scal[s].breakdown = bad ? 1 : 0;
-      atomicAdd(ndone, 1);
-      const SubDesc& sd = d.subs[s];
-      atomicAdd(&counters[0], (unsigned long long)t);
-      atomicAdd(&counters[1], cg_bytes(sd, t, sizeof(T)));
-    }
-    return;
-  }
-  const double beta = t == 0 ? 0.0 : rz / scal[s].rz[(t - 1) & 1];
-  if (leader) scal[s].rz[t & 1] = rz;
-  const SubDesc sd = d.subs[s];
-  Slots<T, CPT, Q> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  lds_zero(lds, sl.G * kPlanes * sl.SP);
-  __syncthreads();
-  const T tb = T(beta);
-  const bool first = t == 0;
-  double a0 = 0.0;
-  const T* __restrict__ rb = r + sl.off;
-  const T* __restrict__ pob = pold + sl.off;
-  T* __restrict__ pnb = pnew + sl.off;
-  T* __restrict__ qb = q + sl.off;
-  auto fetch = [=](uint32_t li, bool) { return Pair<T>{at(rb, li), at(pob, li)}; };
-  auto make = [=](Pair<T> v, uint32_t li, bool own, bool, T dinv) {
-    const T pn = dinv * v.a + (first ? T(0) : tb * v.b);
-    if (own) at(pnb, li) = pn;
-    return pn;
-  };
-  auto store = [&](uint32_t li, bool en, bool, int, int, int, T qv, T pk, T) {
-    if (!en) return;
-    at(qb, li) = qv;
-    a0 += double(pk) * double(qv);
-  };
-  zmarch(sl, lds, fetch, make, store);
-  double acc[1] = {a0};
-  block_sum(acc);
-  if (threadIdx.x == 0) part[3 * blockIdx.x] = acc[0];
-}
-
-template <typename T, int CPT, bool Q>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_cg_update(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
-                                                    int t, T* __restrict__ x, const T* __restrict__ p,
-                                                    T* __restrict__ r, const T* __restrict__ q,
-                                                    double* __restrict__ part, CgScal* __restrict__ scal,
-                                                    int32_t* ndone) {
-  const BlockDesc bd = blocks[blockIdx.x];
-  const int s = bd.s;
-  if (scal[s].done) return;
-  const int b0 = bfirst[s], b1 = bfirst[s + 1];
-  double pq = 0.0;
-  for (int b = b0; b < b1; ++b) pq += part[3 * b];
-  if (!(pq > 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == b0 && threadIdx.x == 0) {
-      scal[s].done = 1;
-      scal[s].iters = t;
-      scal[s].breakdown = 1;
-      atomicAdd(ndone, 1);
-    }
-    return;
-  }
-  const T alpha = T(scal[s].rz[t & 1] / pq);
-  const SubDesc sd = d.subs[s];
-  Slots<T, CPT, Q> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  double a0 = 0.0, a1 = 0.0;
-  cg_pass_b(sl, t == 0, alpha, x, p, r, q, a0, a1);
-  double acc[2] = {a0, a1};
-  block_sum(acc);
-  if (threadIdx.x == 0) {
-    part[3 * blockIdx.x + 1] = acc[0];
-    part[3 * blockIdx.x + 2] = acc[1];
-  }
-}
-
-template <typename T, int CPT>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_add_correction(Dev d, const BlockDesc* blocks, double* __restrict__ u,
-                                                         const T* __restrict__ x, const CgScal* __restrict__ scal) {
-  const BlockDesc bd = blocks[blockIdx.x];
-  if (scal[bd.s].iters <= 0) return;
-  const SubDesc sd = d.subs[bd.s];
-  Slots<T, CPT, false> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
-  double* __restrict__ ub = u + sl.off;
-  const T* __restrict__ xb = x + sl.off;
-#pragma unroll
-  for (int m = 0; m < CPT; ++m) {
-    if (!sl.act[m]) continue;
-    for (int k = sl.z0[m]; k < sl.z1[m]; ++k) {
-      const uint32_t li = sl.c[m] + sl.S * k;
-      at(ub, li) += double(at(xb, li));
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------- fused CG
-
-template <typename T>
-struct Five {
-  T r, w, s, p, x;
-};
-template <typename T>
-struct Three {
-  T r, w, s;
-};
-template <typename T>
-struct Four {
-  T r, w, s, p;
-};
-
-// Sum the block partials of the T members of a team (the blocks that share
-// one subdomain). Every store of the block's sweep completes first (the halo
-// planes the other members read next were written with coherent stores);
-// then the block publishes its partials with coherent stores, each carrying
-// the epoch in its eight lowest mantissa bits, and lanes of the first wave
-// spin (bounded) on the T members' slots until every tag reads the epoch:
-// arrival and data in one round trip. The tag costs at most 2^-44 of a
-// partial's value; the tagged bits are cleared and the partials summed in
-// member order, so every member gets the same sums. Epoch e uses slots
-// (e & 1) with tag (e + 1) mod 256; the slots are zeroed (tag 0) before each
-// launch, and a slot's previous tag is that of epoch e - 2, never equal.
-// A member that waits longer than this (wall clock ticks, 100 MHz: about 1.3 s)
-// for the others gives up and reports a failed barrier (breakdown).
-constexpr unsigned long long kSpinTicks = 1ull << 27;
-constexpr int kTeamSlot = 4;  // doubles per (member, parity) slot
-
-__device__ __forceinline__ double with_tag(double v, unsigned tag) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  return __longlong_as_double((long long)((b & ~0xFFull) | tag));
-}
-__device__ __forceinline__ unsigned tag_of(double v) {
-  return (unsigned)((unsigned long long)__double_as_longlong(v) & 0xFFull);
-}
-
-template <int N>
-__device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int s, int tau, int epoch, int& fail) {
-  static_assert(N <= kTeamSlot, "partials per slot");
-  if (a.team <= 1) return;
-  __shared__ double tval[kMaxTeam * N];
-  __shared__ int tfl[kMaxTeam * N];
-  const unsigned tag = (unsigned)((epoch + 1) & 0xFF);
-  double* const base = a.team_part + (size_t)s * a.team * 2 * kTeamSlot;
-  wait_vm_all();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double* slot = base + ((size_t)tau * 2 + (epoch & 1)) * kTeamSlot;
-#pragma unroll
-    for (int n = 0; n < N; ++n) st_coh(&slot[n], with_tag(v[n], tag));
-  }
-  if (threadIdx.x < a.team * N) {
-    const int m = threadIdx.x / N, n = threadIdx.x - m * N;
-    const double* q = base + ((size_t)m * 2 + (epoch & 1)) * kTeamSlot + n;
-    double val = ld_coh(q);
-    const unsigned long long t0 = wall_clock64();
-    int f = 0;
-    while (tag_of(val) != tag) {
-      if (wall_clock64() - t0 > kSpinTicks) {
-        f = 1;
-        break;
-      }
-      val = ld_coh(q);
-    }
-    tval[threadIdx.x] = with_tag(val, 0u);
-    tfl[threadIdx.x] = f;
-  }
-  __syncthreads();
-  int f = 0;
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-    double acc = 0.0;
-    for (int m = 0; m < a.team; ++m) {
-      acc += tval[m * N + n];
-      f |= tfl[m * N + n];
-    }
-    v[n] = acc;
-  }
-  fail |= f;
-  // tval is rewritten only after the next sweep's barriers
-}
-
-// One block per subdomain (team = 1), or a team of blocks each owning a
-// contiguous range of z-planes (team > 1): the complete preconditioned CG solve of
-// A_s d = r_s from d = 0, then u_s += d. No inter-block communication.
-// The CG is the single-reduction form of Chronopoulos and Gear: with
-// u = D^-1 r and w = A u carried along, one sweep per iteration updates
-//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = D^-1 r
-// pointwise and applies w = A u, and one block reduction yields
-// gamma = r'u, delta = w'u and r'r; then beta = gamma/gamma_old and
-// alpha = gamma / (delta - beta gamma / alpha_old). r, w, s, p are double
-// buffered (halo planes of one segment are read while another writes).
-// COH (a team of more than one block): every load and store of the vectors
-// whose halo planes the team members read is coherent (ld_coh / st_coh), so
-// the team barrier needs no cache maintenance; a fixed instruction form on
-// every plane keeps the prefetch waits exact.
-// RES (uniform z only): 1, p and x stay in LDS for the whole launch; 2, x
-// alone (for z-ranges where both do not fit). A halo plane only needs
-// u = D^-1 (r - alpha (w + beta s)), so p and x are read and written by the
-// thread that owns the node and never by another block; global traffic per CG
-// iteration drops from ten words per node to six (eight with x alone).
-template <typename T, int CPT, bool Q, bool ZU, bool COH, int RES>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* lds = reinterpret_cast<T*>(smem);
-  // block -> (team j, member tau); with 8 | n_sub the members of a team share
-  // blockIdx % 8, i.e. one XCD under round-robin dispatch (shared L2)
-  const int b = blockIdx.x, TM = a.team;
-  int j, tau;
-  if (TM > 1 && (d.geo.n_sub & 7) == 0) {
-    const int slot = b >> 3;
-    j = (b & 7) + 8 * (slot / TM);
-    tau = slot % TM;
-  } else {
-    j = b / TM;
-    tau = b % TM;
-  }
-  const int s = a.order[j];
-  const SubDesc sd = d.subs[s];
-  const int zb0 = (tau * sd.n[2]) / TM, zb1 = ((tau + 1) * sd.n[2]) / TM;
-  Slots<T, CPT, Q> sl;
-  const bool ra = a.rows != 0;
-  slots_init(sl, sd, d.geo, zb0, zb1, true, ra);
-  int epoch = 0, tfail = 0;
-  // buffers chosen with selects, never through an indexed array: pointers
-  // read back from a private array lose their global address space and the
-  // loads become flat loads, which every barrier then waits for
-  T* const r0b = reinterpret_cast<T*>(a.r);
-  T* const r1b = reinterpret_cast<T*>(a.r1);
-  T* const w0b = reinterpret_cast<T*>(a.w0);
-  T* const w1b = reinterpret_cast<T*>(a.w1);
-  T* const s0b = reinterpret_cast<T*>(a.s0);
-  T* const s1b = reinterpret_cast<T*>(a.s1);
-  T* const p0b = reinterpret_cast<T*>(a.p0);
-  T* const p1b = reinterpret_cast<T*>(a.p1);
-  T* __restrict__ x = reinterpret_cast<T*>(a.x);
-  double rr = 0.0, bb = 0.0;
-  for (int b = bfirst[s]; b < bfirst[s + 1]; ++b) {
-    rr += a.res_part[3 * b + 1];
-    bb += a.res_part[3 * b + 2];
-  }
-  const double stop2 = fmax(a.tol_rel * a.tol_rel * rr, a.tol_abs * a.tol_abs * bb);
-  // march planes: the second operand plane only with second-order terms or
-  // wave-owned rows (see zmarch)
-  const int mplanes = RES ? march_planes(Q, ra) : kPlanes;
-  lds_zero(lds, sl.G * mplanes * sl.SP);
-  __syncthreads();
-  // resident p (RES 1) and x: one LDS value per own node, index li - S uz0
-  T* const xres = lds + sl.G * mplanes * sl.SP;
-  T* const pres = xres + (size_t)(zb1 - zb0) * sl.S;
-  const uint32_t plane0 = (uint32_t)(sl.S * zb0);
-  int t = 0, brk = 0;
-  if (RES && (!ZU || (size_t)(sl.G * mplanes * sl.SP + (RES == 1 ? 2 : 1) * (zb1 - zb0) * sl.S) * sizeof(T) >
-                         a.lds_bytes))
-    brk = 1;  // the host sizes the LDS for the largest z-range
-  if (COH != (TM > 1)) brk = 1;  // the host pairs the coherent variant with teams
-  if (!isfinite(rr)) brk = 1;
-  if (ZU && sl.G != 1) brk = 1;  // the host selects ZU only when every block has one segment
-  // wave-owned rows only where the block's waves cover the plane (host checked)
-  if (ra && (!ZU || ra_waves(sd.n[0], sd.n[1], CPT) < 1 || ra_waves(sd.n[0], sd.n[1], CPT) > (int)(blockDim.x >> 6)))
-    brk = 1;
-  if (!brk && rr > stop2 && a.max_inner > 0) {
-    // u0 = D^-1 r0, w0 = A u0, gamma0 = r0'u0, delta0 = w0'u0
-    double g0 = 0.0, d0 = 0.0;
-    {
-      const T* __restrict__ r0 = r0b + sl.off;
-      T* __restrict__ w0 = w0b + sl.off;
-      auto fetch = [=](uint32_t li, bool) { return at(r0, li); };  // r0: written by an earlier launch
-      auto make = [&](T rv, uint32_t, bool own, bool, T dinv) {
-        const T u = dinv * rv;
-        if (own) g0 += double(rv) * double(u);
-        return u;
-      };
-      auto store = [&](uint32_t li, bool en, bool, int, int, int, T wv, T uk, T) {
-        if (!en) return;
-        if constexpr (COH) st_coh(&at(w0, li), wv);
-        else at(w0, li) = wv;
-        d0 += double(wv) * double(uk);
-      };
-      zmarch<ZU>(sl, lds, fetch, make, store);
-    }
-    double acc0[2] = {g0, d0};
-    block_sum(acc0);
-    team_sum(acc0, a, s, tau, epoch++, tfail);
-    double gamma = acc0[0], delta = acc0[1];
-    double alpha = gamma / delta, beta = 0.0;
-    if (!(delta > 0.0) || !isfinite(alpha) || tfail) brk = 1;
-    while (!brk) {
-      const bool odd = (t & 1) != 0;
-      const T* __restrict__ rc = (odd ? r1b : r0b) + sl.off;
-      const T* __restrict__ wc = (odd ? w1b : w0b) + sl.off;
-      const T* __restrict__ sc = (odd ? s1b : s0b) + sl.off;
-      const T* __restrict__ pc = (odd ? p1b : p0b) + sl.off;
-      T* __restrict__ xs = x + sl.off;
-      T* __restrict__ rn_ = (odd ? r0b : r1b) + sl.off;
-      T* __restrict__ wn_ = (odd ? w0b : w1b) + sl.off;
-      T* __restrict__ sn_ = (odd ? s0b : s1b) + sl.off;
-      T* __restrict__ pn_ = (odd ? p0b : p1b) + sl.off;
-      const bool first = t == 0;
-      const T ta = T(alpha), tb = T(beta);
-      // per-thread partial sums in the inner precision (a few dozen terms),
-      // combined across the block in FP64
-      T ag = T(0), ad = T(0), ar = T(0);
-      auto fetch = [=](uint32_t li, bool) {
-        if constexpr (RES == 2) {
-          Four<T> v;
-          if constexpr (COH) {
-            v.r = ld_coh(&at(rc, li));
-            v.w = ld_coh(&at(wc, li));
-            v.s = ld_coh(&at(sc, li));
-          } else {
-            v.r = at(rc, li);
-            v.w = at(wc, li);
-            v.s = at(sc, li);
-          }
-          v.p = at(pc, li);  // p: own planes only, never exchanged
-          return v;
-        } else if constexpr (RES == 1) {
-          Three<T> v;
-          if constexpr (COH) {
-            v.r = ld_coh(&at(rc, li));
-            v.w = ld_coh(&at(wc, li));
-            v.s = ld_coh(&at(sc, li));
-          } else {
-            v.r = at(rc, li);
-            v.w = at(wc, li);
-            v.s = at(sc, li);
-          }
-          return v;
-        } else {
-        Five<T> v;
-        if constexpr (COH) {
-          v.r = ld_coh(&at(rc, li));
-          v.w = ld_coh(&at(wc, li));
-          v.s = ld_coh(&at(sc, li));
-          v.p = ld_coh(&at(pc, li));
-        } else {
-          v.r = at(rc, li);
-          v.w = at(wc, li);
-          v.s = at(sc, li);
-          v.p = at(pc, li);
-        }
-        v.x = at(xs, li);  // x: own planes only, never exchanged
-        return v;
-        }
-      };
-      auto make = [&](const auto& v, uint32_t li, bool own, bool, T dinv) {
-        // the first iteration has no previous direction and no iterate (the
-        // buffers may hold anything, so select rather than scale by zero)
-        const T vs = first ? T(0) : v.s;
-        const T sn = v.w + tb * vs;
-        const T rn = v.r - ta * sn;
-        const T un = dinv * rn;
-        if constexpr (RES != 0) {
-          if (own) {
-            const uint32_t q = li - plane0;
-            T pn;
-            if constexpr (RES == 1) {
-              pn = fma(tb, first ? T(0) : pres[q], dinv * v.r);
-              pres[q] = pn;
-            } else {
-              pn = fma(tb, first ? T(0) : v.p, dinv * v.r);
-              at(pn_, li) = pn;
-            }
-            xres[q] = fma(ta, pn, first ? T(0) : xres[q]);
-            if constexpr (COH) {
-              st_coh(&at(sn_, li), sn);
-              st_coh(&at(rn_, li), rn);
-            } else {
-              at(sn_, li) = sn;
-              at(rn_, li) = rn;
-            }
-            ag += rn * un;
-            ar += rn * rn;
-          }
-          return un;
-        } else {
-        // the same rounding as the resident form: explicit fused multiply-adds
-        const T vp = first ? T(0) : v.p, vx = first ? T(0) : v.x;
-        const T pn = fma(tb, vp, dinv * v.r);
-        if (own) {
-          if constexpr (COH) {
-            st_coh(&at(pn_, li), pn);
-            st_coh(&at(sn_, li), sn);
-            st_coh(&at(rn_, li), rn);
-          } else {
-            at(pn_, li) = pn;
-            at(sn_, li) = sn;
-            at(rn_, li) = rn;
-          }
-          at(xs, li) = fma(ta, pn, vx);
-          ag += rn * un;
-          ar += rn * rn;
-        }
-        return un;
-        }
-      };
-      auto store = [&](uint32_t li, bool en, bool, int, int, int, T wv, T uk, T) {
-        if (!en) return;
-        if constexpr (COH) st_coh(&at(wn_, li), wv);
-        else at(wn_, li) = wv;
-        ad += wv * uk;
-      };
-      zmarch<ZU>(sl, lds, fetch, make, store);
-      double acc[3] = {double(ag), double(ad), double(ar)};
-      block_sum(acc);
-      team_sum(acc, a, s, tau, epoch++, tfail);
-      ++t;
-      rr = acc[2];
-      if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(rr) || tfail) {
-        brk = 1;
-        break;
-      }
-      if (!(rr > stop2) || t >= a.max_inner) break;
-      const double gnew = acc[0];
-      beta = gnew / gamma;
-      const double den = acc[1] - beta * gnew / alpha;
-      if (!(den > 0.0)) {
-        brk = 1;
-        break;
-      }
-      alpha = gnew / den;
-      gamma = gnew;
-    }
-  }
-  if (t > 0) {
-    const T* __restrict__ xb = x + sl.off;
-    double* __restrict__ ub = a.u + sl.off;
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      if (!sl.act[m]) continue;
-      for (int k = sl.z0[m]; k < sl.z1[m]; k += 4) {
-        T xv[4];
-        double uv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k + u < sl.z1[m]) {
-            const uint32_t li = sl.c[m] + sl.S * (k + u);
-            xv[u] = RES != 0 ? xres[li - plane0] : at(xb, li);
-            uv[u] = at(ub, li);
-          }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k + u < sl.z1[m]) at(ub, sl.c[m] + sl.S * (k + u)) = uv[u] + double(xv[u]);
-      }
-    }
-  }
-  if (threadIdx.x == 0 && tau == 0) {
-    a.scal[s].iters = t;
-    a.scal[s].breakdown = brk;
-    a.scal[s].done = 1;
-    atomicAdd(&a.iters_total[0], (unsigned long long)t);
-    atomicAdd(&a.iters_total[1], fused_bytes(sd, t, sizeof(T)));
-  }
 }
 
 // ---------------------------------------------------------------------------- exchange
@@ -1427,8 +204,8 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
 // [c nblk / copies, (c + 1) nblk / copies)): res_c = ||f - K u~|| / ||f||, and
 // the largest over the copies (the stopping quantity). dev_out: [max res,
 // r'r, f'f of the worst copy, res_0 .. res_{copies-1}].
-__global__ void k_final_norm(const double* __restrict__ part, int nblk, int copies, double* dev_out,
-                             double* host_out) {
+__global__ void k_final_norm(const double* __restrict__ part, int nblk, int copies, const int32_t* flags,
+                             double* dev_out, double* host_out) {
   const int per = nblk / copies;
   double worst = 0.0, wr = 0.0, wf = 0.0;
   for (int c = 0; c < copies; ++c) {
@@ -1450,7 +227,10 @@ __global__ void k_final_norm(const double* __restrict__ part, int nblk, int copi
     dev_out[0] = worst;
     dev_out[1] = wr;
     dev_out[2] = wf;
-    if (host_out) host_out[0] = worst;
+    if (host_out) {
+      host_out[0] = worst;
+      host_out[1] = flags ? double(*flags) : 0.0;
+    }
   }
 }
 
@@ -1552,37 +332,6 @@ hipError_t launch_grad_density(const Geom& g, const double* psi, double G, doubl
   return hipGetLastError();
 }
 
-#define SOS_DISPATCH_Q(hasq, CALL) \
-  if (hasq) {                       \
-    constexpr bool Q = true;        \
-    CALL;                           \
-  } else {                          \
-    constexpr bool Q = false;       \
-    CALL;                           \
-  }
-
-#define SOS_DISPATCH_CPT(cpt, KERNEL_CALL) \
-  switch (cpt) {                           \
-    case 1: {                              \
-      constexpr int C = 1;                 \
-      KERNEL_CALL;                         \
-    } break;                               \
-    case 2: {                              \
-      constexpr int C = 2;                 \
-      KERNEL_CALL;                         \
-    } break;                               \
-    case 3: {                              \
-      constexpr int C = 3;                 \
-      KERNEL_CALL;                         \
-    } break;                               \
-    case 4: {                              \
-      constexpr int C = 4;                 \
-      KERNEL_CALL;                         \
-    } break;                               \
-    default:                               \
-      return hipErrorInvalidValue;         \
-  }
-
 static dim3 node_grid(const Dev& d, int max_n, int threads) { return dim3((max_n + threads - 1) / threads, d.geo.n_sub); }
 
 hipError_t launch_load_density(const Dev& d, int max_n, const double* drho, double G, double* f_loc,
@@ -1631,34 +380,35 @@ hipError_t launch_cg_init(const Dev& d, const SegLaunch& L, const double* part, 
 
 hipError_t launch_cg_apply(const Dev& d, const SegLaunch& L, int fp32, int t, int max_inner, const void* r,
                            const void* p_old, void* p_new, void* q, double* part, CgScal* scal, int32_t* ndone,
-                           unsigned long long* counters, hipStream_t st) {
+                           unsigned long long* counters, int32_t* flags, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
   if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<float, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds32,
                                                st, d, L.blocks, L.bfirst, t, max_inner, (const float*)r,
                                                (const float*)p_old, (float*)p_new, (float*)q, part, scal, ndone,
-                                               counters));
+                                               counters, flags));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<double, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, L.bfirst, t, max_inner, (const double*)r,
                                                (const double*)p_old, (double*)p_new, (double*)q, part, scal,
-                                               ndone, counters));
+                                               ndone, counters, flags));
   }
   });
   return hipGetLastError();
 }
 
 hipError_t launch_cg_update(const Dev& d, const SegLaunch& L, int fp32, int t, void* x, const void* p, void* r,
-                            const void* q, double* part, CgScal* scal, int32_t* ndone, hipStream_t st) {
+                            const void* q, double* part, CgScal* scal, int32_t* ndone, int32_t* flags,
+                            hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
   if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<float, C, Q>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
                                                L.blocks, L.bfirst, t, (float*)x, (const float*)p, (float*)r,
-                                               (const float*)q, part, scal, ndone));
+                                               (const float*)q, part, scal, ndone, flags));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_update<double, C, Q>), dim3(L.nblocks), dim3(L.threads), 0, st, d,
                                                L.blocks, L.bfirst, t, (double*)x, (const double*)p, (double*)r,
-                                               (const double*)q, part, scal, ndone));
+                                               (const double*)q, part, scal, ndone, flags));
   }
   });
   return hipGetLastError();
@@ -1676,76 +426,10 @@ hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, dou
   return hipGetLastError();
 }
 
-// True when the device's compute units can hold all `blocks` blocks of the
-// kernel at once (occupancy of the kernel alone, dynamic LDS included). The
-// answer for the last (device, kernel, shape) is kept per host thread: the
-// same launch repeats every outer iteration.
-static bool team_grid_resident(const void* fn, int threads, size_t lds, int blocks) {
-  struct Memo {
-    int dev = -1, threads = 0, blocks = 0;
-    const void* fn = nullptr;
-    size_t lds = 0;
-    bool ok = false;
-  };
-  static thread_local Memo memo;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return false;
-  if (memo.dev == dev && memo.fn == fn && memo.threads == threads && memo.lds == lds && memo.blocks == blocks)
-    return memo.ok;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return false;
-  memo = {dev, threads, blocks, fn, lds, (long long)per_cu * cus >= blocks};
-  return memo.ok;
-}
-
-template <typename T, int C, bool Q, bool ZU, int RES = 0>
-static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
-                                   hipStream_t st, bool* plain) {
-  const dim3 grid(d.geo.n_sub * a.team), block(threads);
-  if (plain) {  // query only: would the launch be a plain one?
-    *plain = a.team <= 1 ||
-             team_grid_resident((const void*)k_fused_cg<T, C, Q, ZU, true, RES>, threads, lds, (int)grid.x);
-    return hipSuccess;
-  }
-  if (a.team <= 1) {
-    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, false, RES>), grid, block, lds, st, d, L.bfirst, a);
-    return hipGetLastError();
-  }
-  // team barriers spin: every block of the grid must be resident at once.
-  // When the occupancy of the kernel alone admits the whole grid, a plain
-  // launch dispatches every block at once (and can be captured in a graph);
-  // otherwise the cooperative launch checks residency and fails instead. A
-  // member that still waits too long reports a failed barrier.
-  const void* fn = (const void*)k_fused_cg<T, C, Q, ZU, true, RES>;
-  if (team_grid_resident(fn, threads, lds, (int)grid.x)) {
-    hipLaunchKernelGGL((k_fused_cg<T, C, Q, ZU, true, RES>), grid, block, lds, st, d, L.bfirst, a);
-    return hipGetLastError();
-  }
-  Dev dd = d;
-  const int32_t* bf = L.bfirst;
-  FusedArgs aa = a;
-  void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)lds, st);
-}
-
 hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threads, int cpt, size_t lds,
                            const FusedArgs& a, hipStream_t st, bool* plain) {
   if (a.res && (!fp32 || !a.zu || lds > a.lds_bytes)) return hipErrorInvalidValue;
-  SOS_DISPATCH_Q(d.hasq, {
-    if (fp32 && a.zu && a.res == 1) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 1>(d, L, threads, a.lds_bytes, a, st, plain)));
-    } else if (fp32 && a.zu && a.res == 2) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true, 2>(d, L, threads, a.lds_bytes, a, st, plain)));
-    } else if (fp32 && a.zu) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, true>(d, L, threads, lds, a, st, plain)));
-    } else if (fp32) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<float, C, Q, false>(d, L, threads, lds, a, st, plain)));
-    } else if (a.zu) {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, true>(d, L, threads, lds, a, st, plain)));
-    } else {
-      SOS_DISPATCH_CPT(cpt, return (fused_launch_one<double, C, Q, false>(d, L, threads, lds, a, st, plain)));
-    }
-  });
+  SOS_DISPATCH_CPT(cpt, return launch_fused_cpt<C>(d, L, fp32, threads, lds, a, st, plain));
   return hipSuccess;
 }
 
@@ -1780,9 +464,9 @@ hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, cons
   return hipGetLastError();
 }
 
-hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, double* dev_out, double* host_out,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, nblk, copies, dev_out, host_out);
+hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, const int32_t* flags,
+                             double* dev_out, double* host_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, nblk, copies, flags, dev_out, host_out);
   return hipGetLastError();
 }
 

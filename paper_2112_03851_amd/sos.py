@@ -7,9 +7,11 @@ stated); PyTorch supplies memory and streams only.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -65,6 +67,19 @@ class Stats(C.Structure):
 
 
 _LIB = None
+# Problems still open at interpreter exit are destroyed before the HIP runtime
+# and any profiler attached to it shut down (never from a finaliser that runs
+# during that shutdown).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_problems():
+    for prob in list(_LIVE):
+        try:
+            prob.close()
+        except Exception:
+            pass
 
 
 def declared_functions():
@@ -106,6 +121,8 @@ def lib():
         "sos_set_density": (C.c_int, [P, P]),
         "sos_iterate": (C.c_int, [P, I, C.POINTER(Stats)]),
         "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
+        "sos_history": (C.c_int, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
+        "sos_debug_barrier": (C.c_int, [P, C.c_int64, I]),
         "sos_optimize_robin": (C.c_int, [I, D, D, I, I, I, D, C.c_uint64, C.POINTER(D), C.POINTER(D),
                                          C.POINTER(I)]),
         "sos_destroy": (None, [P]),
@@ -211,6 +228,7 @@ class Problem:
                                  C.byref(o), C.byref(h)))
         self.h = h
         self.precision = prec
+        _LIVE.add(self)
 
     def _per_face(self, v):
         """A per-copy coefficient array expanded to one value per directed face."""
@@ -317,7 +335,7 @@ class Problem:
                                C.byref(st))
         if code not in (SOS_OK, SOS_ENOCONV):
             _check(code)
-        return phi, dict(st.as_dict(), converged=code == SOS_OK)
+        return phi, dict(st.as_dict(), converged=code == SOS_OK, code=code)
 
     def solve_load(self, f_nodes, tol, phi=None):
         import torch
@@ -328,7 +346,7 @@ class Problem:
                                     _ptr(phi, torch.float64), C.byref(st))
         if code not in (SOS_OK, SOS_ENOCONV):
             _check(code)
-        return phi, dict(st.as_dict(), converged=code == SOS_OK)
+        return phi, dict(st.as_dict(), converged=code == SOS_OK, code=code)
 
     def adjoint(self, gphi, tol, want_psi=False):
         """dJ/ddrho per element from dJ/dPhi over all nodes (adjoint Schwarz solve)."""
@@ -379,6 +397,21 @@ class Problem:
         st = Stats()
         _check(lib().sos_iterate(self.h, int(n), C.byref(st)))
         return st.as_dict()
+
+    def history(self):
+        """(outer iteration, relative residual) of every convergence check since
+        the last solve started."""
+        n = C.c_int32()
+        _check(lib().sos_history(self.h, 0, C.byref(n), None, None))
+        outer = (C.c_int32 * max(1, n.value))()
+        res = (C.c_double * max(1, n.value))()
+        _check(lib().sos_history(self.h, n.value, C.byref(n), outer, res))
+        return [(int(outer[i]), float(res[i])) for i in range(n.value)]
+
+    def debug_barrier(self, spin_ticks=0, tag_skew=0):
+        """Failure-handling tests: bound of the team barrier's wait (ticks at
+        100 MHz, 0 = default) and tag_skew = 1 to make every wait end there."""
+        _check(lib().sos_debug_barrier(self.h, int(spin_ticks), int(tag_skew)))
 
     def residual(self, want_phi=True):
         import torch

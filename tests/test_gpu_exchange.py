@@ -29,10 +29,13 @@ def _one_iteration(case, prob, q, seed):
     orc = S.SchwarzOracle(case.part, case.p, "lu", q_face=q)
     ur = orc.subdomain_solves(fs, lam0)
     lr = orc.exchange(ur, lam0)
+    eu = max(np.abs(u1[s] - ur[s]).max() / np.abs(ur[s]).max() for s in range(case.part.n_sub))
+    el = max(np.abs(lam1[fc] - lr[fc]).max() / np.abs(lr[fc]).max() for fc in range(len(lr)))
+    print("max rel error: u", eu, "lambda", el, flush=True)
     for s in range(case.part.n_sub):
-        assert np.abs(u1[s] - ur[s]).max() <= 1e-9 * np.abs(ur[s]).max(), s
+        assert np.abs(u1[s] - ur[s]).max() <= 1e-10 * np.abs(ur[s]).max(), s
     for fc in range(len(lr)):
-        assert np.abs(lam1[fc] - lr[fc]).max() <= 1e-9 * np.abs(lr[fc]).max(), fc
+        assert np.abs(lam1[fc] - lr[fc]).max() <= 1e-10 * np.abs(lr[fc]).max(), fc
 
 
 def test_exchange_uses_coefficients_set_after_setup():

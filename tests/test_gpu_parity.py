@@ -80,10 +80,13 @@ def test_one_outer_iteration_matches_oracle_step(q):
     orc = S.SchwarzOracle(case.part, case.p, "lu", q_face=q)
     ur = orc.subdomain_solves(fs, lam0)
     lr = orc.exchange(ur, lam0)
+    eu = max(np.abs(u1[s] - ur[s]).max() / np.abs(ur[s]).max() for s in range(case.part.n_sub))
+    el = max(np.abs(lam1[fc] - lr[fc]).max() / np.abs(lr[fc]).max() for fc in range(len(lr)))
+    print("max rel error: u", eu, "lambda", el, flush=True)
     for s in range(case.part.n_sub):
-        assert np.abs(u1[s] - ur[s]).max() <= 1e-9 * np.abs(ur[s]).max(), s
+        assert np.abs(u1[s] - ur[s]).max() <= 1e-10 * np.abs(ur[s]).max(), s
     for fc in range(len(lr)):
-        assert np.abs(lam1[fc] - lr[fc]).max() <= 1e-9 * np.abs(lr[fc]).max(), fc
+        assert np.abs(lam1[fc] - lr[fc]).max() <= 1e-10 * np.abs(lr[fc]).max(), fc
 
 
 def test_plain_fp64_c1_matches_oracle_iteration_count_and_iterate():
@@ -102,7 +105,9 @@ def test_plain_fp64_c1_matches_oracle_iteration_count_and_iterate():
     print("oracle outer", n_or, "gpu outer (inner 1e-13)", st["outer_iters"], "inner", st["inner_iters"], flush=True)
     assert st["converged"] and st["rel_residual"] <= wl.tol
     assert abs(st["outer_iters"] - n_or) <= 1
-    assert np.abs(phi - U).max() <= 1e-6 * np.abs(U).max()
+    e_it = np.abs(phi - U).max() / np.abs(U).max()
+    print("c1 iterate: max rel difference from the oracle's iterate", e_it, flush=True)
+    assert e_it <= 1e-6
     # the paper's inner tolerance 1e-10 (Sec. 6) perturbs every local solve by
     # up to cond(A_s) * 1e-10: the count stays within 2 percent
     prob10 = case.problem(precision="fp64", mode="stepwise")
@@ -240,7 +245,8 @@ def test_full_size_c2_batched_sampled_nodes_match_direct():
     idx = rng.choice(free, 4096, replace=False)
     err = np.abs(phi[idx] - ud[idx]).max() / np.abs(ud).max()
     print("c2 sampled max rel error vs direct", err, flush=True)
-    assert err <= 1e-5
+    # 10 tol: see the error bound in test_gpu_scale.py
+    assert err <= 10 * wl.tol
     assert np.all(phi[case.mesh.dirichlet_mask()] == 0.0)
 
 

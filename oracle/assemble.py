@@ -26,16 +26,6 @@ def assemble_stiffness(mesh: BoxMesh):
     return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
 
 
-def assemble_mass(mesh: BoxMesh):
-    _, Me, _ = fe.element_matrices(mesh.h)
-    conn = mesh.element_nodes()
-    rows = np.repeat(conn, 27, axis=1).ravel()
-    cols = np.tile(conn, (1, 27)).ravel()
-    vals = np.tile(Me.ravel(), mesh.n_elem)
-    n = mesh.n_nodes
-    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
-
-
 def reduced_stiffness(mesh: BoxMesh):
     """Stiffness restricted to the unknown (non-Dirichlet) nodes."""
     K = assemble_stiffness(mesh)

@@ -292,6 +292,19 @@ int sos_set_density(sos_ctx* ctx, const double* drho_elem);
 int sos_iterate(sos_ctx* ctx, int32_t n, sos_stats* stats);
 /* Global relative residual and glued solution of the current state. */
 int sos_residual(sos_ctx* ctx, double* phi_nodes, double* rel_residual);
+/* sos_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same global residual (and, if phi_nodes != NULL, the glued solution),
+ * with its working vectors (the averaged copies, the local residuals, the
+ * block partials, the result words) in a fixed scratch array of 48 MiB per
+ * GPU that the library holds from its first set-up on that GPU until the
+ * process ends, instead of the context's workspaces. Calls no allocating
+ * routine. Contexts of more than about 3.1 M local unknowns (2 FP64 vectors
+ * plus partials beyond 48 MiB) return SOS_EINVAL. Every context on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU race (the
+ * library serialises nothing); a call overwrites every scratch value it reads,
+ * so no clearing is needed. Host output rel_residual as sos_residual. */
+int sos_residual_noalloc(sos_ctx* ctx, double* phi_nodes, double* rel_residual);
 /* Residual history (Sec. 6 stops on the global residual): the outer
  * iteration count and relative residual of every convergence check since the
  * last solve started (or sos_set_state); sos_iterate appends. *n receives the

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,36 @@ struct Seg {
   int32_t* d_bfirst = nullptr;
   SegLaunch L{};
 };
+
+// Scratch memory of the allocation-free entry points: one array per GPU, in
+// device memory from the moment the library's code object is loaded on that
+// GPU until the process ends. Host code never uses the name `scratch` as an
+// address (it is a host-side stand-in there); it uses the device address that
+// hipGetSymbolAddress returns, resolved once per device at set-up.
+constexpr size_t kScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on first use
+// per device, with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SOS_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SOS_ESTATE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(SOS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SOS_OK;
+}
 
 }  // namespace
 
@@ -110,6 +141,7 @@ struct sos_ctx {
   // team barrier wait bound and tag skew (sos_debug_barrier)
   uint64_t spin_ticks = 1ull << 27;
   int32_t tag_skew = 0;
+  void* scratch = nullptr;  // device address of this device's scratch array
   // (outer iteration, relative residual) of every check since the last solve start
   std::vector<int32_t> hist_outer;
   std::vector<double> hist_res;
@@ -1079,6 +1111,10 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
     return fail(SOS_ESTATE, "no usable HIP device");
   }
   c->lds_limit = prop.sharedMemPerBlock;
+  if ((rc = scratch_address(&c->scratch))) {
+    release(c);
+    return rc;
+  }
   {
     const size_t ex_lds =
         2 * sizeof(double) * (size_t)(c->max_face_na + 4) * (size_t)(exchange_rows(c->max_face_na) + 4);
@@ -1347,6 +1383,32 @@ int sos_residual(sos_ctx* c, double* phi, double* res) {
   int rc = phi ? write_phi(c, phi) : enqueue_check(c, nullptr);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (res) *res = c->h_res[0];
+  return SOS_OK;
+}
+
+int sos_residual_noalloc(sos_ctx* c, double* phi, double* res) {
+  if (!c) return fail(SOS_EINVAL, "ctx is NULL");
+  if (!c->scratch) return fail(SOS_ESTATE, "no scratch address for this context's device");
+  // ut and rho (local layout), the assemble partials and the result words
+  const size_t n_vec = (size_t)align64(c->n_local);
+  const size_t n_part = (size_t)align64(2 * (int64_t)c->n_norm_blocks);
+  const size_t need = (2 * n_vec + n_part + 4 + (size_t)c->geo.copies) * sizeof(double);
+  if (need > kScratchBytes)
+    return fail(SOS_EINVAL, "the global residual of %lld local unknowns needs %zu bytes of scratch; the "
+                "allocation-free variant holds at most %zu bytes (about %zu local unknowns)",
+                (long long)c->n_local, need, kScratchBytes, kScratchBytes / (2 * sizeof(double)) - 4096);
+  double* ut = static_cast<double*>(c->scratch);
+  double* rho = ut + n_vec;
+  double* part = rho + n_vec;
+  double* dres = part + n_part;
+  hipStream_t st = c->stream;
+  if (phi) HIPCHK(launch_fill(phi, c->n_nodes, 0.0, st));
+  HIPCHK(launch_glue(c->dev, c->max_n, c->u, ut, st));
+  HIPCHK(launch_local_residual(c->dev, c->seg.L, ut, c->f, rho, st));
+  HIPCHK(launch_assemble_norm(c->dev, c->max_n, rho, c->f, ut, phi, part, st));
+  HIPCHK(launch_final_norm(part, c->n_norm_blocks, c->geo.copies, c->flags, dres, c->d_hres, st));
+  HIPCHK(hipStreamSynchronize(st));
   if (res) *res = c->h_res[0];
   return SOS_OK;
 }

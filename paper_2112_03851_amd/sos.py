@@ -122,6 +122,7 @@ def lib():
         "sos_iterate": (C.c_int, [P, I, C.POINTER(Stats)]),
         "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_history": (C.c_int, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
+        "sos_residual_noalloc": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_debug_barrier": (C.c_int, [P, C.c_int64, I]),
         "sos_optimize_robin": (C.c_int, [I, D, D, I, I, I, D, C.c_uint64, C.POINTER(D), C.POINTER(D),
                                          C.POINTER(I)]),
@@ -397,6 +398,16 @@ class Problem:
         st = Stats()
         _check(lib().sos_iterate(self.h, int(n), C.byref(st)))
         return st.as_dict()
+
+    def residual_noalloc(self, want_phi=True):
+        """sos_residual with its working vectors in the library's fixed scratch
+        array (no device allocation by the library)."""
+        import torch
+        phi = torch.empty(self.n_nodes, dtype=torch.float64, device="cuda") if want_phi else None
+        res = C.c_double()
+        _sync_torch()
+        _check(lib().sos_residual_noalloc(self.h, _ptr(phi) if phi is not None else None, C.byref(res)))
+        return phi, res.value
 
     def history(self):
         """(outer iteration, relative residual) of every convergence check since

@@ -81,6 +81,11 @@ def measured_traffic(launch_bytes, st, workload_name):
     return None
 
 
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def host_info():
     """Host CPUs of this machine: logical CPUs, the ones this process may use,
     and the model name."""
@@ -134,7 +139,9 @@ def cpu_baseline(wl, budget_s, phi_gpu, n_outer_solve, n_outer_basis):
         el = time.perf_counter() - t0
         return n, el, (time.process_time() - c0) / el
 
+    log(f"cpu baseline: oracle set up in {setup_s:.1f} s")
     n, el, busy = sample(budget_s)
+    log(f"cpu baseline: {n} outer iterations in {el:.1f} s")
     one = None
     try:
         from threadpoolctl import threadpool_limits
@@ -150,6 +157,7 @@ def cpu_baseline(wl, budget_s, phi_gpu, n_outer_solve, n_outer_basis):
                      f"scaled by {n_outer_solve} outer iterations per solve ({n_outer_basis})",
            "outer_iters_per_s": n / el, "one_thread": one, **host_info()}
     if phi_gpu is not None:
+        log("cpu baseline: the oracle's direct solve for the error of the GPU result")
         t0 = time.perf_counter()
         ud = D.solve_direct(m, f, "fdm")
         out["direct_solve_s"] = time.perf_counter() - t0
@@ -295,7 +303,10 @@ def main():
     # reference solve (the first solve also tunes the fused kernel's block
     # shape): outer iterations per solve, and the roofline from HIP events
     # around every fused launch (eager launches)
+    log(f"workload {wl.name}: reference solve (eager, HIP events; the first solve tunes the block shape)")
     phi, ref = prob.solve(drho, wl.tol)
+    log(f"reference solve: {ref['outer_iters']} outer iterations, {ref['seconds']:.2f} s, block {ref['block']} x "
+        f"{ref['cols_per_thread']}, team {ref['team']}, resident {ref['resident']}")
     if not ref["converged"]:
         raise RuntimeError(f"batched reference solve did not converge: {ref}")
     phi_np = phi.cpu().numpy()
@@ -338,6 +349,7 @@ def main():
                 state["solves"] += 1
                 restart()
 
+    log(f"{args.warmup} warm-up and {args.steps} timed steps of {k} outer iterations")
     restart()
     for _ in range(args.warmup):
         step()
@@ -349,6 +361,7 @@ def main():
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    log(f"timed: {args.steps * k} outer iterations in {el:.2f} s, {state['solves']} solves completed")
     if not state["res"] or max(state["res"]) > wl.tol:
         raise RuntimeError(f"a timed solve missed the tolerance: {state['res']}")
     outer_timed = args.steps * k
@@ -369,6 +382,7 @@ def main():
         # subdomains, inner stop 1e-12 ||b_s||) over the first outer iterations
         p64 = Problem(wl.ne, wl.lengths, wl.bc, cuts=wl.cuts, p=rp, q=rq, G=wl.G, precision="fp64", mode="stepwise",
                       check_every=1, inner_tol=0.0, inner_abs=1e-12, max_inner=2000, timing=1)
+        log(f"plain FP64 form: {args.plain_outer} outer iterations")
         p64.set_density(drho)
         p64.set_state(zu, zl)
         torch.cuda.synchronize()

@@ -150,7 +150,8 @@ typedef struct {
                              two kernels read and write per iteration          */
   int32_t block;          /* workgroup size used by the fused CG kernel         */
   int32_t cols_per_thread;/* x-y columns per thread of the fused CG kernel      */
-  int32_t team;           /* blocks per subdomain of the fused CG kernel        */
+  int32_t team;           /* blocks per subdomain of the fused CG kernel (the
+                             largest team; see sos_teams)                      */
   int32_t wave_rows;      /* 1: each wave of the fused CG kernel owns whole
                              x-rows of the plane (one barrier per plane)       */
   int32_t resident;       /* the fused CG kernel keeps in LDS: 1 p and x,
@@ -216,6 +217,19 @@ int sos_set_opts(sos_ctx* ctx, const sos_opts* opts);
  * *n receives their number; if s_j_axis != NULL it receives 4 int32 per face:
  * s, j, axis, side (host memory, caller-owned, 4*n entries). */
 int sos_faces(const sos_ctx* ctx, int32_t* n, int32_t* s_j_axis_side);
+
+/* Team sizes of the batched fused CG kernel, one per subdomain (host memory,
+ * n_sub entries, sos_layout order): the number of workgroups that share the
+ * subdomain's inner solve (Sec. 6 solves each subdomain with one diagonally
+ * preconditioned CG; a team splits its z-planes and meets at one barrier per
+ * CG iteration). The autotuner picks them per size bucket: subdomains whose
+ * node counts differ by more than 1.5x fall into three buckets of equal
+ * width in log size, each with its own team size. */
+int sos_teams(const sos_ctx* ctx, int32_t* teams);
+/* Set them (1..8, at most the subdomain's z-planes; SOS_EINVAL otherwise):
+ * the current block shape and these teams are used from now on without
+ * autotuning, until sos_set_opts changes a launch option. */
+int sos_set_teams(sos_ctx* ctx, const int32_t* teams);
 
 /* Layout of the concatenated subdomain vectors: n_sub; if offsets != NULL it
  * receives n_sub+1 int64 offsets, if dims != NULL 3*n_sub int32 local node

@@ -98,7 +98,14 @@ struct sos_ctx {
   SubDesc* d_subs = nullptr;
   FaceDesc* d_faces = nullptr;
   ExPair* d_expairs = nullptr;  // the pairs resolved for the exchange kernel
-  int32_t* d_order = nullptr;
+  // fused kernel: team size per subdomain, its size bucket (0 = largest), and
+  // the block -> (subdomain, member) table
+  std::vector<int32_t> sub_team, sub_bucket;
+  int n_buckets = 1;
+  std::vector<TeamSlot> fmap;
+  TeamSlot* d_fmap = nullptr;
+  size_t fmap_cap = 0;
+  bool fmap_dirty = true;
   Seg seg;
   // workspaces
   double *u = nullptr, *f = nullptr, *lam = nullptr, *ut = nullptr, *rho = nullptr;
@@ -160,7 +167,7 @@ void release(sos_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
   for (auto e : c->gevents) hipEventDestroy(e);
-  void* ptrs[] = {c->d_subs, c->d_faces, c->d_expairs, c->d_order, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
+  void* ptrs[] = {c->d_subs, c->d_faces, c->d_expairs, c->d_fmap, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_part,
                   c->scal, c->ndone, c->counters, c->flags};
@@ -324,20 +331,95 @@ int fused_shape(sos_ctx* c, int threads, int cpt = 0, int ra = 0, int res = 0) {
 // marches a single segment, so the uniform-z kernel variant applies.
 bool fused_one_segment(const sos_ctx* c) {
   if (c->fused_ra) return true;  // wave-owned rows: one segment by construction
-  const int T = c->fused_team;
-  for (auto& s : c->subs)
+  for (size_t i = 0; i < c->subs.size(); ++i) {
+    const SubDesc& s = c->subs[i];
+    const int T = c->sub_team[i];
     for (int tau = 0; tau < T; ++tau) {
       const int zlen = ((tau + 1) * s.n[2]) / T - (tau * s.n[2]) / T;
       if (march_segments(s.n[0], s.n[1], zlen, c->fused_threads, c->fused_cpt) != 1) return false;
     }
+  }
   return true;
 }
 
-int set_team(sos_ctx* c, int team) {
-  if (team < 1 || team > kMaxTeam) return fail(SOS_EINVAL, "team must be in [1, %d]", kMaxTeam);
-  for (auto& s : c->subs)
-    if (s.n[2] < team) return fail(SOS_EINVAL, "team of %d blocks exceeds a subdomain's %d z-planes", team, s.n[2]);
-  c->fused_team = team;
+// Team sizes per subdomain (every copy of a subdomain gets the same).
+int set_teams(sos_ctx* c, const std::vector<int32_t>& teams) {
+  if (teams.size() != c->subs.size()) return fail(SOS_EINVAL, "one team size per subdomain expected");
+  int mx = 1;
+  for (size_t i = 0; i < teams.size(); ++i) {
+    const int t = teams[i];
+    if (t < 1 || t > kMaxTeam) return fail(SOS_EINVAL, "team must be in [1, %d]", kMaxTeam);
+    if (c->subs[i].n[2] < t)
+      return fail(SOS_EINVAL, "team of %d blocks exceeds subdomain %zu's %d z-planes", t, i, c->subs[i].n[2]);
+    mx = std::max(mx, t);
+  }
+  c->sub_team = teams;
+  c->fused_team = mx;
+  c->fmap_dirty = true;
+  invalidate_graph(c);
+  return SOS_OK;
+}
+
+int set_team(sos_ctx* c, int team) { return set_teams(c, std::vector<int32_t>(c->subs.size(), team)); }
+
+// One team size per size bucket (teams[b] for bucket b).
+int set_bucket_teams(sos_ctx* c, const std::vector<int32_t>& teams) {
+  std::vector<int32_t> t(c->subs.size());
+  for (size_t i = 0; i < t.size(); ++i) t[i] = teams[c->sub_bucket[i]];
+  return set_teams(c, t);
+}
+
+// Size buckets of the subdomains (0 = largest): one bucket when the node
+// counts differ by at most 1.5x, else three of equal width in log size.
+void make_buckets(sos_ctx* c) {
+  int64_t lo = INT64_MAX, hi = 0;
+  std::vector<int64_t> n(c->subs.size());
+  for (size_t i = 0; i < n.size(); ++i) {
+    n[i] = (int64_t)c->subs[i].n[0] * c->subs[i].n[1] * c->subs[i].n[2];
+    lo = std::min(lo, n[i]);
+    hi = std::max(hi, n[i]);
+  }
+  c->sub_bucket.assign(n.size(), 0);
+  c->n_buckets = 1;
+  if (hi <= lo * 3 / 2) return;
+  c->n_buckets = 3;
+  const double span = std::log((double)hi / (double)lo);
+  for (size_t i = 0; i < n.size(); ++i) {
+    const int k = std::min(2, (int)(3.0 * std::log((double)n[i] / (double)lo) / span));
+    c->sub_bucket[i] = 2 - k;
+  }
+}
+
+// The fused kernel's block table: teams in the order of c->order (largest
+// subdomain first). With a team of two or more blocks anywhere, the members of
+// every team share blockIdx % 8 (one XCD under round-robin dispatch, so their
+// halo planes and partials meet in one L2): each team goes to the shortest of
+// eight queues and block b = 8 * position + queue, the queues padded with idle
+// blocks. Uploaded before launches (never during a graph capture).
+int ensure_fmap(sos_ctx* c) {
+  if (!c->fmap_dirty) return SOS_OK;
+  std::vector<TeamSlot>& m = c->fmap;
+  m.clear();
+  if (c->fused_team <= 1) {
+    for (int32_t s : c->order) m.push_back({s, 0, 1, 0});
+  } else {
+    std::vector<std::vector<TeamSlot>> q(8);
+    for (int32_t s : c->order) {
+      size_t best = 0;
+      for (size_t k = 1; k < q.size(); ++k)
+        if (q[k].size() < q[best].size()) best = k;
+      const int T = c->sub_team[s];
+      for (int tau = 0; tau < T; ++tau) q[best].push_back({s, tau, T, 0});
+    }
+    size_t len = 0;
+    for (auto& v : q) len = std::max(len, v.size());
+    m.assign(8 * len, TeamSlot{-1, 0, 1, 0});
+    for (size_t k = 0; k < q.size(); ++k)
+      for (size_t i = 0; i < q[k].size(); ++i) m[8 * i + k] = q[k][i];
+  }
+  if (m.size() > c->fmap_cap) return fail(SOS_EINVAL, "fused block table of %zu entries exceeds %zu", m.size(), c->fmap_cap);
+  HIPCHK(hipMemcpy(c->d_fmap, m.data(), m.size() * sizeof(TeamSlot), hipMemcpyHostToDevice));
+  c->fmap_dirty = false;
   return SOS_OK;
 }
 
@@ -385,14 +467,16 @@ std::vector<Shape> fused_candidates(const sos_ctx* c) {
 // (2: p and x, 1: x).
 size_t fused_res_lds(const sos_ctx* c, int words) {
   size_t need = 0;
-  const int T = c->fused_team;
   const int planes = march_planes(c->dev.hasq != 0, c->fused_ra != 0);
-  for (auto& s : c->subs)
+  for (size_t i = 0; i < c->subs.size(); ++i) {
+    const SubDesc& s = c->subs[i];
+    const int T = c->sub_team[i];
     for (int tau = 0; tau < T; ++tau) {
       const size_t zlen = (size_t)(((tau + 1) * s.n[2]) / T - (tau * s.n[2]) / T);
       const size_t sp = (size_t)(s.n[0] + 2 * kPad) * (size_t)(s.n[1] + 2 * kPad);
       need = std::max(need, (planes * sp + words * zlen * (size_t)s.n[0] * (size_t)s.n[1]) * sizeof(float));
     }
+  }
   return need;
 }
 
@@ -407,7 +491,7 @@ std::string tune_key(const sos_ctx* c) {
     for (int a = 0; a < 3; ++a) mix((uint64_t)s.n[a]);
   mix((uint64_t)c->subs.size());
   char buf[160];
-  snprintf(buf, sizeof buf, "gfx950|%s|%016llx|tol%.3g|abs%.3g|max%d", c->fp32 ? "fp32" : "fp64",
+  snprintf(buf, sizeof buf, "gfx950|v2|%s|%016llx|tol%.3g|abs%.3g|max%d", c->fp32 ? "fp32" : "fp64",
            (unsigned long long)h, c->opts.inner_tol, c->opts.inner_abs, c->opts.max_inner);
   return buf;
 }
@@ -419,7 +503,9 @@ std::string tune_cache_path() {
   return std::string(home ? home : "/tmp") + "/.cache/sos_autotune.jsonl";
 }
 
-bool tune_lookup(const std::string& key, int* threads, int* cpt, int* team, int* ra, int* res) {
+// One cached tuning result: "teams" holds one team size per size bucket (an
+// entry with a single "team" is a uniform team, one bucket).
+bool tune_lookup(const std::string& key, int* threads, int* cpt, std::vector<int32_t>* teams, int* ra, int* res) {
   FILE* f = fopen(tune_cache_path().c_str(), "r");
   if (!f) return false;
   char line[512];
@@ -429,37 +515,44 @@ bool tune_lookup(const std::string& key, int* threads, int* cpt, int* team, int*
     if (!strstr(line, pat.c_str())) continue;
     const char* t = strstr(line, "\"threads\": ");
     const char* k = strstr(line, "\"cpt\": ");
-    const char* m = strstr(line, "\"team\": ");
-    const char* w = strstr(line, "\"rows\": ");
-    if (t && k && m && sscanf(t + 11, "%d", threads) == 1 && sscanf(k + 7, "%d", cpt) == 1 &&
-        sscanf(m + 8, "%d", team) == 1) {
-      found = true;
-      *ra = 0;
-      *res = 0;
-      if (w) (void)sscanf(w + 8, "%d", ra);
-      const char* v = strstr(line, "\"resident\": ");
-      if (v) (void)sscanf(v + 12, "%d", res);
+    const char* m = strstr(line, "\"teams\": [");
+    if (!t || !k || !m || sscanf(t + 11, "%d", threads) != 1 || sscanf(k + 7, "%d", cpt) != 1) continue;
+    std::vector<int32_t> tv;
+    for (const char* q = m + 10; *q && *q != ']';) {
+      char* e = nullptr;
+      const long v = strtol(q, &e, 10);
+      if (e == q) break;
+      tv.push_back((int32_t)v);
+      q = e;
+      while (*q == ',' || *q == ' ') ++q;
     }
+    if (tv.empty()) continue;
+    found = true;
+    *teams = tv;
+    *ra = 0;
+    *res = 0;
+    const char* w = strstr(line, "\"rows\": ");
+    if (w) (void)sscanf(w + 8, "%d", ra);
+    const char* v = strstr(line, "\"resident\": ");
+    if (v) (void)sscanf(v + 12, "%d", res);
   }
   fclose(f);
   return found;
 }
 
-void tune_store(const std::string& key, int threads, int cpt, int team, int ra, int res, double ms) {
+void tune_store(const std::string& key, int threads, int cpt, const std::vector<int32_t>& teams, int ra, int res,
+                double ms) {
   std::string path = tune_cache_path();
   const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    std::string dir = path.substr(0, slash);
-    std::string cmd;
-    (void)cmd;
-    mkdir(dir.c_str(), 0755);
-  }
+  if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);
   FILE* f = fopen(path.c_str(), "a");
   if (!f) return;
+  std::string tl;
+  for (size_t i = 0; i < teams.size(); ++i) tl += (i ? ", " : "") + std::to_string(teams[i]);
   fprintf(f,
-          "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"team\": %d, \"rows\": %d, \"resident\": %d, "
+          "{\"key\": \"%s\", \"threads\": %d, \"cpt\": %d, \"teams\": [%s], \"rows\": %d, \"resident\": %d, "
           "\"ms\": %.4f}\n",
-          key.c_str(), threads, cpt, team, ra, res, ms);
+          key.c_str(), threads, cpt, tl.c_str(), ra, res, ms);
   fclose(f);
 }
 
@@ -530,7 +623,8 @@ int enqueue_check(sos_ctx* c, double* phi) {
 
 FusedArgs fused_args(sos_ctx* c) {
   FusedArgs a;
-  a.order = c->d_order;
+  a.fmap = c->d_fmap;
+  a.nblocks = (int32_t)c->fmap.size();
   a.res_part = c->part;
   a.tol_rel = c->opts.inner_tol;
   a.tol_abs = c->opts.inner_abs;
@@ -693,6 +787,10 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
   c->kernel_launches = 0;
   const bool batched = c->opts.mode == SOS_BATCHED;
   const bool log = log_checks();
+  if (batched) {
+    int rc = ensure_fmap(c);
+    if (rc) return rc;
+  }
   // HIP events recorded inside a graph cannot be read back with
   // hipEventElapsedTime: timed runs launch eagerly; so do cooperative team
   // launches (not captured)
@@ -817,77 +915,112 @@ int reset_state(sos_ctx* c) {
   return SOS_OK;
 }
 
-// Autotuner: time every candidate block shape of the fused kernel on the
-// first inner solve of the current load (u = 0, lambda = 0), keep the
-// fastest, cache it per (arch, subdomain geometry, precision, inner tolerance).
+// Autotuner: time every candidate block shape of the fused kernel with every
+// uniform team size on the first inner solve of the current load (u = 0,
+// lambda = 0), keep the fastest; then, for subdomains of uneven size (more
+// than one size bucket), search each bucket's team size in turn (smallest
+// bucket first, two passes) with the others fixed. The result is cached per (arch,
+// subdomain geometry, precision, inner tolerance).
 int autotune(sos_ctx* c) {
   if (c->tuned) return SOS_OK;
   c->tuned = true;
   const std::string key = tune_key(c);
-  int th = 0, cp = 0, tm = 0, ra = 0, res = 0;
-  if (tune_lookup(key, &th, &cp, &tm, &ra, &res) && fused_shape(c, th, cp, ra, res && c->opts.resident) == SOS_OK &&
-      set_team(c, tm) == SOS_OK)
+  int th = 0, cp = 0, ra = 0, res = 0;
+  std::vector<int32_t> bt;
+  if (tune_lookup(key, &th, &cp, &bt, &ra, &res) && (int)bt.size() == c->n_buckets &&
+      fused_shape(c, th, cp, ra, res && c->opts.resident) == SOS_OK && set_bucket_teams(c, bt) == SOS_OK)
     return SOS_OK;
   // block shapes are tuned unless fixed by opts.block, team sizes unless fixed by opts.team
   std::vector<Shape> shapes;
   if (c->opts.block) shapes.push_back({c->fused_threads, c->fused_cpt, c->fused_ra, c->fused_res});
   else shapes = fused_candidates(c);
+  auto team_ok = [&](int t, int bucket) {  // every subdomain of the bucket (-1: all) has 2t planes
+    for (size_t i = 0; i < c->subs.size(); ++i)
+      if ((bucket < 0 || c->sub_bucket[i] == bucket) && c->subs[i].n[2] < 2 * t) return false;
+    return true;
+  };
   std::vector<int> teams;
   if (c->opts.team) teams.push_back(c->opts.team);
   else
-    for (int t : {1, 2, 4, 8}) {
-      bool ok = true;
-      for (auto& s : c->subs) ok &= s.n[2] >= 2 * t;
-      if (ok) teams.push_back(t);
-    }
+    for (int t : {1, 2, 4, 8})
+      if (team_ok(t, -1)) teams.push_back(t);
   hipStream_t st = c->stream;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  // fastest of three launches of the current shape and teams (INFINITY: unusable)
+  auto time_config = [&](double* out) -> int {
+    *out = INFINITY;
+    int rc = ensure_fmap(c);
+    if (rc) return rc;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
+      HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
+                             c->fused_team > 1 ? c->team_part : nullptr, st));
+      HIPCHK(hipEventRecord(e0, st));
+      if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
+                          st) != hipSuccess) {
+        (void)hipGetLastError();  // e.g. a team grid that cannot be co-resident
+        *out = INFINITY;
+        return SOS_OK;
+      }
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      *out = std::min(*out, (double)ms);
+    }
+    return SOS_OK;
+  };
   double best = INFINITY;
-  int bt = c->fused_threads, bc = c->fused_cpt, bm = c->fused_team, br = c->fused_ra, bs = c->fused_res;
+  Shape bs{c->fused_threads, c->fused_cpt, c->fused_ra, c->fused_res};
+  std::vector<int32_t> bteams(c->n_buckets, c->fused_team);
+  int rc = SOS_OK;
   for (int team : teams)
     for (auto& cd : shapes) {
       if (fused_shape(c, cd.threads, cd.cpt, cd.ra, cd.res) != SOS_OK || set_team(c, team) != SOS_OK) continue;
       if (cd.res && !fused_args(c).res) continue;  // p and x do not fit in LDS with this team
-      double ms_min = INFINITY;
-      bool ok = true;
-      for (int rep = 0; rep < 3 && ok; ++rep) {  // fastest of three
-        HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
-        HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
-                               team > 1 ? c->team_part : nullptr, st));
-        HIPCHK(hipEventRecord(e0, st));
-        if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
-                            st) != hipSuccess) {
-          (void)hipGetLastError();  // e.g. a team grid that cannot be co-resident
-          ok = false;
-          break;
-        }
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        ms_min = std::min(ms_min, (double)ms);
-      }
-      if (ok && ms_min < best) {
-        best = ms_min;
-        bt = cd.threads;
-        bc = cd.cpt;
-        br = cd.ra;
-        bs = cd.res;
-        bm = team;
+      double ms = INFINITY;
+      if ((rc = time_config(&ms))) break;
+      if (ms < best) {
+        best = ms;
+        bs = cd;
+        bteams.assign(c->n_buckets, team);
       }
     }
+  // per-bucket team sizes with the best shape: two passes of coordinate
+  // descent, smallest bucket first (shrinking the small subdomains' teams
+  // frees co-resident blocks that the large ones' teams then need)
+  if (!rc && c->n_buckets > 1 && !c->opts.team && std::isfinite(best) &&
+      fused_shape(c, bs.threads, bs.cpt, bs.ra, bs.res) == SOS_OK) {
+    for (int pass = 0; pass < 2 * c->n_buckets && !rc; ++pass) {
+      const int b = c->n_buckets - 1 - pass % c->n_buckets;
+      for (int t : {1, 2, 4, 8}) {
+        if (t == bteams[b] || !team_ok(t, b)) continue;
+        std::vector<int32_t> trial = bteams;
+        trial[b] = t;
+        if (set_bucket_teams(c, trial) != SOS_OK) continue;
+        if (bs.res && !fused_args(c).res) continue;
+        double ms = INFINITY;
+        if ((rc = time_config(&ms))) break;
+        if (ms < best) {
+          best = ms;
+          bteams = trial;
+        }
+      }
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (rc) return rc;
   HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
   HIPCHK(hipStreamSynchronize(st));
-  int rc = fused_shape(c, bt, bc, br, bs);
-  if (!rc) rc = set_team(c, bm);
+  rc = fused_shape(c, bs.threads, bs.cpt, bs.ra, bs.res);
+  if (!rc) rc = set_bucket_teams(c, bteams);
   if (rc) return rc;
   c->tune_ms = best;
   invalidate_graph(c);
-  tune_store(key, bt, bc, bm, br, bs, best);
+  tune_store(key, bs.threads, bs.cpt, bteams, bs.ra, bs.res, best);
   return SOS_OK;
 }
 
@@ -1129,7 +1262,10 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
     release(c);
     return rc;
   }
-  // fused order: largest first
+  // fused order: largest first; block table capacity: sum of teams (at most
+  // kMaxTeam per subdomain) plus the padding of eight queues
+  make_buckets(c);
+  c->fmap_cap = (size_t)kMaxTeam * g.n_sub + 8 * kMaxTeam;
   c->order.resize(g.n_sub);
   for (int s = 0; s < g.n_sub; ++s) c->order[s] = s;
   std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) {
@@ -1141,7 +1277,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   Dev tmp{nullptr, nullptr, g, 0, 0};
   c->n_norm_blocks = assemble_blocks(tmp, c->max_n);
   if ((rc = dalloc(&c->d_subs, c->subs.size())) || (rc = dalloc(&c->d_faces, c->faces.size())) ||
-      (rc = dalloc(&c->d_expairs, c->pairs.size())) || (rc = dalloc(&c->d_order, c->order.size())) ||
+      (rc = dalloc(&c->d_expairs, c->pairs.size())) || (rc = dalloc(&c->d_fmap, c->fmap_cap)) ||
       (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
       (rc = dalloc(&c->u, c->n_local)) || (rc = dalloc(&c->f, c->n_local)) || (rc = dalloc(&c->lam, c->n_lam)) ||
       (rc = dalloc(&c->b, c->n_local)) ||
@@ -1187,7 +1323,6 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   if (e == hipSuccess && !c->faces.empty())
     e = hipMemcpy(c->d_faces, c->faces.data(), c->faces.size() * sizeof(FaceDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = upload_expairs(c);
-  if (e == hipSuccess) e = hipMemcpy(c->d_order, c->order.data(), c->order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(c->seg.d_blocks, c->seg.blocks.data(), c->seg.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -1242,6 +1377,20 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
     c->tuned = o->block != 0 && o->team != 0;
   }
   invalidate_graph(c);
+  return SOS_OK;
+}
+
+int sos_teams(const sos_ctx* c, int32_t* teams) {
+  if (!c || !teams) return fail(SOS_EINVAL, "NULL argument");
+  for (size_t i = 0; i < c->sub_team.size(); ++i) teams[i] = c->sub_team[i];
+  return SOS_OK;
+}
+
+int sos_set_teams(sos_ctx* c, const int32_t* teams) {
+  if (!c || !teams) return fail(SOS_EINVAL, "NULL argument");
+  int rc = set_teams(c, std::vector<int32_t>(teams, teams + c->subs.size()));
+  if (rc) return rc;
+  c->tuned = true;  // keep these teams and the current block shape
   return SOS_OK;
 }
 

@@ -941,14 +941,15 @@ __device__ __forceinline__ unsigned tag_of(double v) {
 }
 
 template <int N>
-__device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int s, int tau, int epoch, int& fail) {
+__device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int s, int tau, int TM, int epoch,
+                                         int& fail) {
   static_assert(N <= kTeamSlot, "partials per slot");
-  if (a.team <= 1) return;
+  if (TM <= 1) return;
   __shared__ double tval[kMaxTeam * N];
   __shared__ int tfl[kMaxTeam * N];
   const unsigned tag = (unsigned)((epoch + 1) & 0xFF);
   const unsigned want = (unsigned)((epoch + 1 + a.tag_skew) & 0xFF);
-  double* const base = a.team_part + (size_t)s * a.team * 2 * kTeamSlot;
+  double* const base = a.team_part + (size_t)s * kMaxTeam * 2 * kTeamSlot;
   wait_vm_all();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -956,7 +957,7 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 #pragma unroll
     for (int n = 0; n < N; ++n) st_coh(&slot[n], with_tag(v[n], tag));
   }
-  if (threadIdx.x < a.team * N) {
+  if (threadIdx.x < TM * N) {
     const int m = threadIdx.x / N, n = threadIdx.x - m * N;
     const double* q = base + ((size_t)m * 2 + (epoch & 1)) * kTeamSlot + n;
     double val = ld_coh(q);
@@ -977,7 +978,7 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 #pragma unroll
   for (int n = 0; n < N; ++n) {
     double acc = 0.0;
-    for (int m = 0; m < a.team; ++m) {
+    for (int m = 0; m < TM; ++m) {
       acc += tval[m * N + n];
       f |= tfl[m * N + n];
     }
@@ -1010,19 +1011,11 @@ template <typename T, int CPT, bool Q, bool ZU, bool COH, int RES>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int32_t* __restrict__ bfirst, FusedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  // block -> (team j, member tau); with 8 | n_sub the members of a team share
-  // blockIdx % 8, i.e. one XCD under round-robin dispatch (shared L2)
-  const int b = blockIdx.x, TM = a.team;
-  int j, tau;
-  if (TM > 1 && (d.geo.n_sub & 7) == 0) {
-    const int slot = b >> 3;
-    j = (b & 7) + 8 * (slot / TM);
-    tau = slot % TM;
-  } else {
-    j = b / TM;
-    tau = b % TM;
-  }
-  const int s = a.order[j];
+  // block -> (subdomain s, member tau of its team of TM blocks), host-built:
+  // the members of a team share blockIdx % 8, i.e. one XCD (shared L2)
+  const TeamSlot ts = a.fmap[blockIdx.x];
+  if (ts.s < 0) return;  // padding
+  const int s = ts.s, tau = ts.tau, TM = ts.T;
   const SubDesc sd = d.subs[s];
   const int zb0 = (tau * sd.n[2]) / TM, zb1 = ((tau + 1) * sd.n[2]) / TM;
   Slots<T, CPT, Q> sl;
@@ -1073,7 +1066,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   if (RES && (!ZU || (size_t)(sl.G * mplanes * sl.SP + (RES == 1 ? 2 : 1) * (zb1 - zb0) * sl.S) * sizeof(T) >
                          a.lds_bytes))
     brk |= kBrkLaunch;  // the host sizes the LDS for the largest z-range
-  if (COH != (TM > 1)) brk |= kBrkLaunch;  // the host pairs the coherent variant with teams
+  if (!COH && TM > 1) brk |= kBrkLaunch;  // the host picks the coherent variant whenever a team has 2+ blocks
   if (!isfinite(rr) || !isfinite(bb)) brk |= kBrkNonFinite;
   if (ZU && sl.G != 1) brk |= kBrkLaunch;  // the host selects ZU only when every block has one segment
   // wave-owned rows only where the block's waves cover the plane (host checked)
@@ -1102,7 +1095,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
     }
     double acc0[2] = {g0, d0};
     block_sum(acc0);
-    team_sum(acc0, a, s, tau, epoch++, tfail);
+    team_sum(acc0, a, s, tau, TM, epoch++, tfail);
     double gamma = acc0[0], delta = acc0[1];
     double alpha = gamma / delta, beta = 0.0;
     if (tfail) brk |= kBrkBarrier;
@@ -1228,7 +1221,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       zmarch<ZU>(sl, lds, fetch, make, store);
       double acc[3] = {double(ag), double(ad), double(ar)};
       block_sum(acc);
-      team_sum(acc, a, s, tau, epoch++, tfail);
+      team_sum(acc, a, s, tau, TM, epoch++, tfail);
       ++t;
       rr = acc[2];
       if (tfail) {

@@ -34,7 +34,7 @@ static bool team_grid_resident(const void* fn, int threads, size_t lds, int bloc
 template <typename T, int C, bool Q, bool ZU, int RES = 0>
 static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads, size_t lds, const FusedArgs& a,
                                    hipStream_t st, bool* plain) {
-  const dim3 grid(d.geo.n_sub * a.team), block(threads);
+  const dim3 grid(a.nblocks), block(threads);
   if (plain) {  // query only: would the launch be a plain one?
     *plain = a.team <= 1 ||
              team_grid_resident((const void*)k_fused_cg<T, C, Q, ZU, true, RES>, threads, lds, (int)grid.x);

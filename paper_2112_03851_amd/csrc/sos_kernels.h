@@ -104,10 +104,17 @@ hipError_t launch_cg_update(const Dev& d, const SegLaunch& L, int fp32, int t, v
 // did not break down.
 hipError_t launch_add_correction(const Dev& d, const SegLaunch& L, int fp32, double* u, const void* x,
                                  const CgScal* scal, hipStream_t st);
-// The fused inner solve: one block per subdomain (order gives the block->subdomain
-// map) runs its whole CG and adds the correction to u.
+// Member tau of the team of T blocks that solves subdomain s (s < 0: an idle
+// block that exits at once, padding the grid so that a team's members share
+// blockIdx % 8, i.e. one XCD under round-robin dispatch).
+struct TeamSlot {
+  int32_t s, tau, T, pad;
+};
+// The fused inner solve: every block of the grid (fmap gives the block ->
+// (subdomain, member) map, larger subdomains first) runs its part of a whole CG
+// and adds the correction to u.
 struct FusedArgs {
-  const int32_t* order;    // n_sub subdomains, largest first
+  const TeamSlot* fmap;    // nblocks entries
   const double* res_part;  // residual partials (segmented launch L)
   double tol_rel, tol_abs;
   int32_t max_inner;
@@ -115,8 +122,9 @@ struct FusedArgs {
   double* u;
   CgScal* scal;
   unsigned long long* iters_total;  // [0] CG iterations, [1] algorithmic bytes
-  int32_t team;                     // blocks per subdomain (1: no inter-block sync)
-  double* team_part;                // n_sub * team * 2 * 4 tagged partial sums (cleared by
+  int32_t nblocks;                  // grid size (teams plus idle padding blocks)
+  int32_t team;                     // the largest team (1: no inter-block sync anywhere)
+  double* team_part;                // n_sub * kMaxTeam * 2 * 4 tagged partial sums (cleared by
                                     // the residual kernel before each launch)
   int32_t zu;                       // every block marches one segment (uniform z variant)
   int32_t rows;                     // wave-owned rows (see ra_rows): one barrier per plane

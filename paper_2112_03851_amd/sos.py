@@ -122,6 +122,8 @@ def lib():
         "sos_iterate": (C.c_int, [P, I, C.POINTER(Stats)]),
         "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_history": (C.c_int, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
+        "sos_teams": (C.c_int, [P, C.POINTER(I)]),
+        "sos_set_teams": (C.c_int, [P, C.POINTER(I)]),
         "sos_residual_noalloc": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_debug_barrier": (C.c_int, [P, C.c_int64, I]),
         "sos_optimize_robin": (C.c_int, [I, D, D, I, I, I, D, C.c_uint64, C.POINTER(D), C.POINTER(D),
@@ -408,6 +410,18 @@ class Problem:
         _sync_torch()
         _check(lib().sos_residual_noalloc(self.h, _ptr(phi) if phi is not None else None, C.byref(res)))
         return phi, res.value
+
+    def teams(self):
+        """Team size of the fused CG kernel per subdomain."""
+        n = len(self.layout()["dims"])
+        out = (C.c_int32 * n)()
+        _check(lib().sos_teams(self.h, out))
+        return np.array(out, np.int32)
+
+    def set_teams(self, teams):
+        """Fix the team size of every subdomain (and the current block shape)."""
+        arr = (C.c_int32 * len(teams))(*[int(t) for t in teams])
+        _check(lib().sos_set_teams(self.h, arr))
 
     def history(self):
         """(outer iteration, relative residual) of every convergence check since

@@ -107,7 +107,9 @@ def test_plain_fp64_c1_matches_oracle_iteration_count_and_iterate():
     assert abs(st["outer_iters"] - n_or) <= 1
     e_it = np.abs(phi - U).max() / np.abs(U).max()
     print("c1 iterate: max rel difference from the oracle's iterate", e_it, flush=True)
-    assert e_it <= 1e-6
+    # both run the same 435 outer iterations; the inner solves' 1e-13 residual
+    # perturbs each by far less than the FP64 bound 1e-10 (measured 2.7e-13)
+    assert e_it <= 1e-10
     # the paper's inner tolerance 1e-10 (Sec. 6) perturbs every local solve by
     # up to cond(A_s) * 1e-10: the count stays within 2 percent
     prob10 = case.problem(precision="fp64", mode="stepwise")
@@ -178,7 +180,8 @@ def test_fixed_point_equals_direct_solution_ragged_partition():
         phi, st = prob.solve(torch.tensor(drho, device="cuda"), tol)
         err = np.abs(phi.cpu().numpy() - ud).max() / np.abs(ud).max()
         print(prec, mode, st["outer_iters"], err, flush=True)
-        assert st["converged"] and err <= 1e-8
+        # run to 1e-12 / 1e-11: the fixed point to 1e-10 (measured 8e-13, 7e-12)
+        assert st["converged"] and err <= 1e-10
 
 
 @pytest.mark.parametrize("team", [0, 4])

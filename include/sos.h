@@ -131,6 +131,12 @@ typedef struct {
                           LDS for the whole launch where they fit (uniform
                           z-ranges; with block != 0 it does, the autotuner
                           tries both); 0: never                             */
+  int32_t march;       /* axis every subdomain is marched along (set up once):
+                          0 (default) z, or for a subdomain whose x-y node
+                          plane exceeds 4096 nodes the axis across its
+                          smallest node plane; 1, 2, 3: x, y, z for all.
+                          The other two axes keep their global order; see
+                          sos_axes                                         */
 } sos_opts;
 
 typedef struct {
@@ -167,8 +173,8 @@ int sos_opts_default(sos_opts* opts, int32_t precision);
  * bad options), build subdomain and directed-face descriptors (one Robin
  * datum per directed interface face), allocate device workspaces on the
  * current HIP device (SOS_ENOMEM), SOS_ESTATE without a usable device. Every
- * subdomain's x-y node plane ((2*ex+1)*(2*ey+1), ex, ey its element counts)
- * must hold at most 4096 nodes (SOS_EINVAL otherwise). *out is NULL on
+ * subdomain's node plane across its marched axis (opts.march) must hold at
+ * most 4096 nodes (SOS_EINVAL otherwise). *out is NULL on
  * failure; on success the caller releases it with sos_destroy. */
 int sos_setup(const sos_mesh* mesh, const sos_partition* part, const sos_robin* robin,
               const sos_opts* opts, sos_ctx** out);
@@ -218,6 +224,11 @@ int sos_set_opts(sos_ctx* ctx, const sos_opts* opts);
  * s, j, axis, side (host memory, caller-owned, 4*n entries). */
 int sos_faces(const sos_ctx* ctx, int32_t* n, int32_t* s_j_axis_side);
 
+/* Local axis order of every subdomain: perm[3*s + a] = the global axis (0 x,
+ * 1 y, 2 z) of local axis a; local axis 2 is the one the kernels march along
+ * (host memory, 3*n_sub entries). */
+int sos_axes(const sos_ctx* ctx, int32_t* perm);
+
 /* Team sizes of the batched fused CG kernel, one per subdomain (host memory,
  * n_sub entries, sos_layout order): the number of workgroups that share the
  * subdomain's inner solve (Sec. 6 solves each subdomain with one diagonally
@@ -232,11 +243,13 @@ int sos_teams(const sos_ctx* ctx, int32_t* teams);
 int sos_set_teams(sos_ctx* ctx, const int32_t* teams);
 
 /* Layout of the concatenated subdomain vectors: n_sub; if offsets != NULL it
- * receives n_sub+1 int64 offsets, if dims != NULL 3*n_sub int32 local node
- * counts (x, y, z) and if lo != NULL 3*n_sub int32 global node indices of
- * each subdomain's first local node. Local node (i, j, k) of s sits at
- * offsets[s] + i + nx*(j + ny*k). Face f's datum (sos_get_state) sits at
- * face_off[f] if face_off != NULL (n_faces+1 int64). */
+ * receives n_sub+1 int64 offsets, if dims != NULL 3*n_sub int32 node counts
+ * along each subdomain's local axes 0, 1, 2 (sos_axes: global x, y, z unless
+ * a subdomain marches along another axis) and if lo != NULL 3*n_sub int32
+ * global node indices (x, y, z) of each subdomain's first local node. Local
+ * node (i, j, k) of s sits at offsets[s] + i + n0*(j + n1*k). Face f's datum
+ * (sos_get_state) sits at face_off[f] if face_off != NULL (n_faces+1 int64),
+ * its nodes along the face's tangential global axes, the lower one fastest. */
 int sos_layout(const sos_ctx* ctx, int32_t* n_sub, int64_t* offsets, int32_t* dims,
                int32_t* lo, int64_t* face_off);
 

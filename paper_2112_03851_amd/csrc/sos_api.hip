@@ -205,6 +205,7 @@ int check_opts(const sos_opts* o) {
   if (o->wave_rows != 0 && o->wave_rows != 1) return fail(SOS_EINVAL, "opts.wave_rows must be 0 or 1");
   if (o->wave_rows && !o->block) return fail(SOS_EINVAL, "opts.wave_rows needs opts.block");
   if (o->resident != 0 && o->resident != 1) return fail(SOS_EINVAL, "opts.resident must be 0 or 1");
+  if (o->march < 0 || o->march > 3) return fail(SOS_EINVAL, "opts.march must be 0 (automatic), 1, 2 or 3");
   return SOS_OK;
 }
 
@@ -350,7 +351,8 @@ int set_teams(sos_ctx* c, const std::vector<int32_t>& teams) {
     const int t = teams[i];
     if (t < 1 || t > kMaxTeam) return fail(SOS_EINVAL, "team must be in [1, %d]", kMaxTeam);
     if (c->subs[i].n[2] < t)
-      return fail(SOS_EINVAL, "team of %d blocks exceeds subdomain %zu's %d z-planes", t, i, c->subs[i].n[2]);
+      return fail(SOS_EINVAL, "team of %d blocks exceeds subdomain %zu's %d z-planes (marched planes)", t, i,
+                  c->subs[i].n[2]);
     mx = std::max(mx, t);
   }
   c->sub_team = teams;
@@ -570,6 +572,53 @@ int dalloc_v(void** p, size_t bytes) {
   return SOS_OK;
 }
 
+// The local axis order of every subdomain (its descriptors are built in
+// global order first). The marched axis is z unless the subdomain's x-y node
+// plane holds more than kMaxPlane nodes, then the axis across the smallest
+// node plane; march (1, 2, 3) forces x, y or z for every subdomain. The other
+// two axes keep their global order (the lower one fastest).
+void choose_axes(sos_ctx* c, int march) {
+  for (auto& d : c->subs) {
+    int m = 2;
+    if (march) {
+      m = march - 1;
+    } else if ((int64_t)d.n[0] * d.n[1] > kMaxPlane) {
+      int64_t best = INT64_MAX;
+      for (int g = 2; g >= 0; --g) {
+        const int64_t plane = (int64_t)d.n[(g + 1) % 3] * d.n[(g + 2) % 3];
+        if (plane < best) {
+          best = plane;
+          m = g;
+        }
+      }
+    }
+    int perm[3], k = 0;
+    for (int g = 0; g < 3; ++g)
+      if (g != m) perm[k++] = g;
+    perm[2] = m;
+    const SubDesc o = d;
+    for (int a = 0; a < 3; ++a) {
+      const int g = perm[a];
+      d.n[a] = o.n[g];
+      d.klo[a] = o.klo[g];
+      d.ne2[a] = o.ne2[g];
+      d.face[2 * a] = o.face[2 * g];
+      d.face[2 * a + 1] = o.face[2 * g + 1];
+      d.perm[a] = g;
+      d.iperm[g] = a;
+      d.ks[a] = c->geo.ks[g];
+      d.ms[a] = c->geo.ms[g];
+    }
+    // a face datum runs along its tangential axis of lower global index first
+    d.tswap = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+      if (perm[t1] > perm[t2]) d.tswap |= 1 << a;
+    }
+    d.pad = 0;
+  }
+}
+
 // The exchange kernel's pair descriptors from the host face and subdomain
 // descriptors (again after every change of the Robin coefficients).
 hipError_t upload_expairs(sos_ctx* c) {
@@ -580,12 +629,14 @@ hipError_t upload_expairs(sos_ctx* c) {
     const FaceDesc& G = c->faces[F.opp];
     ExPair P{};
     const int ax = F.axis, ta = ax == 0 ? 1 : 0, tb = ax == 2 ? 1 : 2;
+    // strides of the global axes in each side's local layout
     auto place = [&](const FaceDesc& X, int64_t* base, int64_t* sa, int64_t* sb) {
       const SubDesc& sd = c->subs[X.s];
       const int64_t st[3] = {1, sd.n[0], (int64_t)sd.n[0] * sd.n[1]};
-      *sa = st[ta];
-      *sb = st[tb];
-      *base = sd.off + (int64_t)(X.side ? sd.n[ax] - 1 : 0) * st[ax];
+      *sa = st[sd.iperm[ta]];
+      *sb = st[sd.iperm[tb]];
+      const int la = sd.iperm[ax];
+      *base = sd.off + (int64_t)(X.side ? sd.n[la] - 1 : 0) * st[la];
     };
     place(F, &P.base_s, &P.sa_s, &P.sb_s);
     place(G, &P.base_j, &P.sa_j, &P.sb_j);
@@ -598,10 +649,10 @@ hipError_t upload_expairs(sos_ctx* c) {
     P.msb = c->geo.ms[tb];
     P.ksa = c->geo.ks[ta];
     P.ksb = c->geo.ks[tb];
-    P.kla = sd.klo[ta];
-    P.klb = sd.klo[tb];
-    P.nea = sd.ne2[ta];
-    P.neb = sd.ne2[tb];
+    P.kla = sd.klo[sd.iperm[ta]];
+    P.klb = sd.klo[sd.iperm[tb]];
+    P.nea = sd.ne2[sd.iperm[ta]];
+    P.neb = sd.ne2[sd.iperm[tb]];
     P.na = F.na;
     P.nb = F.nb;
     v.push_back(P);
@@ -1193,6 +1244,7 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
     F.opp = dj.face[2 * F.axis + (1 - F.side)];
     if (F.s < F.j) c->pairs.push_back((int32_t)(&F - &c->faces[0]));
   }
+  choose_axes(c, opts->march);
   // independent copies of the problem: subdomains, faces and vectors repeat
   // copy after copy (copy c's subdomain s is c * n_sub + s)
   {
@@ -1362,6 +1414,7 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
   if (rc) return rc;
   if ((o->precision == SOS_FP32_INNER) != (c->fp32 != 0)) return fail(SOS_EINVAL, "precision is fixed at setup");
   if (o->stream && o->stream != c->stream) return fail(SOS_EINVAL, "the stream is fixed at setup");
+  if (o->march != c->opts.march) return fail(SOS_EINVAL, "the march axes are fixed at setup");
   const int old_block = c->opts.block, old_team = c->opts.team, old_rows = c->opts.wave_rows,
             old_res = c->opts.resident;
   const double old_tol = c->opts.inner_tol, old_abs = c->opts.inner_abs;
@@ -1377,6 +1430,13 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
     c->tuned = o->block != 0 && o->team != 0;
   }
   invalidate_graph(c);
+  return SOS_OK;
+}
+
+int sos_axes(const sos_ctx* c, int32_t* perm) {
+  if (!c || !perm) return fail(SOS_EINVAL, "NULL argument");
+  for (size_t i = 0; i < c->subs.size(); ++i)
+    for (int a = 0; a < 3; ++a) perm[3 * i + a] = c->subs[i].perm[a];
   return SOS_OK;
 }
 

@@ -172,10 +172,11 @@ __device__ __forceinline__ void slots_init(Slots<T, CPT, Q>& sl, const SubDesc& 
   sl.uz0 = zb0;
   sl.uz1 = zb1;
   sl.seglen = (zlen + sl.G - 1) / sl.G;
-  const T ksx = T(geo.ks[0]), msx = T(geo.ms[0]);
-  const T ksy = T(geo.ks[1]), msy = T(geo.ms[1]);
-  sl.zks = T(geo.ks[2]);
-  sl.zms = T(geo.ms[2]);
+  (void)geo;
+  const T ksx = T(d.ks[0]), msx = T(d.ms[0]);
+  const T ksy = T(d.ks[1]), msy = T(d.ms[1]);
+  sl.zks = T(d.ks[2]);
+  sl.zms = T(d.ms[2]);
   sl.kx1 = T(-8) * ksx;
   sl.mx1 = T(2) * msx;
   sl.ky1 = T(-8) * ksy;
@@ -525,25 +526,34 @@ struct Bound {
 
 // Robin data added to the local right-hand side at node (i, j, k).
 struct LamOff {
-  int64_t o[6];  // lambda offset per (axis, side) face, -1 if none
+  int64_t o[6];  // lambda offset per (local axis, side) face, -1 if none
+  int32_t tswap; // SubDesc::tswap
 };
 
 __device__ __forceinline__ LamOff lam_offsets(const Dev& d, const SubDesc& sd) {
   LamOff L;
 #pragma unroll
   for (int f = 0; f < 6; ++f) L.o[f] = sd.face[f] >= 0 ? d.faces[sd.face[f]].lam_off : -1;
+  L.tswap = sd.tswap;
   return L;
+}
+
+// Node (t1, t2) of a face datum (t1 < t2 the local tangential axes, extents
+// n1, n2): stored with the tangential axis of lower global index fastest.
+__device__ __forceinline__ int64_t face_index(int t1, int t2, int n1, int n2, bool swap) {
+  return swap ? t2 + (int64_t)n2 * t1 : t1 + (int64_t)n1 * t2;
 }
 
 __device__ __forceinline__ double lam_terms(const LamOff& L, const double* lam, int i, int j, int k, int nx,
                                             int ny, int nz) {
   double a = 0.0;
-  if (i == 0 && L.o[0] >= 0) a += lam[L.o[0] + j + (int64_t)ny * k];
-  if (i == nx - 1 && L.o[1] >= 0) a += lam[L.o[1] + j + (int64_t)ny * k];
-  if (j == 0 && L.o[2] >= 0) a += lam[L.o[2] + i + (int64_t)nx * k];
-  if (j == ny - 1 && L.o[3] >= 0) a += lam[L.o[3] + i + (int64_t)nx * k];
-  if (k == 0 && L.o[4] >= 0) a += lam[L.o[4] + i + (int64_t)nx * j];
-  if (k == nz - 1 && L.o[5] >= 0) a += lam[L.o[5] + i + (int64_t)nx * j];
+  const bool s0 = (L.tswap & 1) != 0, s1 = (L.tswap & 2) != 0, s2 = (L.tswap & 4) != 0;
+  if (i == 0 && L.o[0] >= 0) a += lam[L.o[0] + face_index(j, k, ny, nz, s0)];
+  if (i == nx - 1 && L.o[1] >= 0) a += lam[L.o[1] + face_index(j, k, ny, nz, s0)];
+  if (j == 0 && L.o[2] >= 0) a += lam[L.o[2] + face_index(i, k, nx, nz, s1)];
+  if (j == ny - 1 && L.o[3] >= 0) a += lam[L.o[3] + face_index(i, k, nx, nz, s1)];
+  if (k == 0 && L.o[4] >= 0) a += lam[L.o[4] + face_index(i, j, nx, ny, s2)];
+  if (k == nz - 1 && L.o[5] >= 0) a += lam[L.o[5] + face_index(i, j, nx, ny, s2)];
   return a;
 }
 

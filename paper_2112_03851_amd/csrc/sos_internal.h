@@ -11,20 +11,29 @@ constexpr int kMaxCols = 8;       // max x-y columns per thread in a z-march
 constexpr int kPad = 2;           // zero padding around an LDS plane (stencil radius)
 
 // One subdomain: a box of elements. Its unknowns are the kept nodes of the
-// closed box (outer Dirichlet planes removed), numbered x fastest.
+// closed box (outer Dirichlet planes removed), numbered along its local axes
+// 0 (fastest), 1, 2 (the marched axis): local axis a is global axis perm[a].
+// Fields marked "local" are in local axis order, the others in global order.
 struct SubDesc {
   int64_t off;      // offset of local node 0 in the concatenated vectors
-  int32_t n[3];     // kept nodes per axis
-  int32_t klo[3];   // closure index (0..2*ne) of local node 0 per axis
-  int32_t ne2[3];   // 2 * elements per axis = closure index of the last node
-  int32_t lo[3];    // global node index of local node 0 per axis
-  int32_t pidx[3];  // position in the partition grid
-  int32_t e0[3];    // first element per axis
-  int32_t face[6];  // directed face (s <- j) id for (axis, side), -1 if none
-  double elo[3];    // Robin coefficient at closure node 0 per axis (0 if none)
-  double ehi[3];    // Robin coefficient at closure node ne2 per axis
-  double qlo[3];    // second-order coefficient q at closure node 0 per axis (0 if none)
-  double qhi[3];    // second-order coefficient q at closure node ne2 per axis
+  int32_t n[3];     // local: kept nodes per axis
+  int32_t klo[3];   // local: closure index (0..2*ne) of local node 0 per axis
+  int32_t ne2[3];   // local: 2 * elements per axis = closure index of the last node
+  int32_t lo[3];    // global: global node index of local node 0 per axis
+  int32_t pidx[3];  // global: position in the partition grid
+  int32_t e0[3];    // global: first element per axis
+  int32_t face[6];  // local: directed face (s <- j) id for (axis, side), -1 if none
+  int32_t perm[3];  // global axis of local axis a
+  int32_t iperm[3]; // local axis of global axis g
+  int32_t tswap;    // bit a: the Robin datum of a local-axis-a face runs along its
+                    // second local tangential axis fastest (global axis order)
+  int32_t pad;
+  double ks[3];     // local: 1/(3h) per axis (scale of the 1D stiffness stencil)
+  double ms[3];     // local: h/30 per axis (scale of the 1D mass stencil)
+  double elo[3];    // local: Robin coefficient at closure node 0 per axis (0 if none)
+  double ehi[3];    // local: Robin coefficient at closure node ne2 per axis
+  double qlo[3];    // local: second-order coefficient q at closure node 0 per axis (0 if none)
+  double qhi[3];    // local: second-order coefficient q at closure node ne2 per axis
   int32_t copy;     // index of the problem copy this subdomain belongs to (batched copies)
   int32_t sbase;    // index of that copy's first subdomain
 };

@@ -120,27 +120,34 @@ __global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restric
 
 // ---------------------------------------------------------------------------- glue and residual
 
+// Global node index (per global axis) of local node (i, j, k) of sd.
+__device__ __forceinline__ void global_node(const SubDesc& sd, int i, int j, int k, int (&G)[3]) {
+  const int li[3] = {i, j, k};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) G[sd.perm[a]] = sd.lo[sd.perm[a]] + li[a];
+}
+
 // Visit the subdomain copies of local node (i, j, k) of sd in ascending
-// subdomain order: fn(global index of the copy in the local layout).
+// subdomain order: fn(index of the copy in the concatenated local layout).
+// Along every global axis the node has one copy, or two where it lies on an
+// interface plane (the lower subdomain's first); each copy's local index
+// follows from the global node through that subdomain's own axis order.
 template <class Fn>
 __device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i, int j, int k, Fn&& fn) {
   const int li[3] = {i, j, k};
-  int p0[3], i0[3], i1[3], nc[3];
+  int G[3];
+  global_node(sd, i, j, k, G);
+  int p0[3], nc[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    nc[a] = 1;
-    p0[a] = sd.pidx[a];
-    i0[a] = li[a];
-    i1[a] = 0;
+  for (int g = 0; g < 3; ++g) {
+    const int a = sd.iperm[g];
+    nc[g] = 1;
+    p0[g] = sd.pidx[g];
     if (li[a] == 0 && sd.face[2 * a] >= 0) {
-      const int jn = d.faces[sd.face[2 * a]].j;
-      nc[a] = 2;
-      p0[a] = sd.pidx[a] - 1;
-      i0[a] = d.subs[jn].n[a] - 1;
-      i1[a] = li[a];
+      nc[g] = 2;
+      p0[g] = sd.pidx[g] - 1;
     } else if (li[a] == sd.n[a] - 1 && sd.face[2 * a + 1] >= 0) {
-      nc[a] = 2;
-      i1[a] = 0;
+      nc[g] = 2;
     }
   }
   const int Px = d.geo.nparts[0], Py = d.geo.nparts[1];
@@ -149,8 +156,9 @@ __device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i
       for (int cx = 0; cx < nc[0]; ++cx) {
         const int s2 = sd.sbase + (p0[0] + cx) + Px * ((p0[1] + cy) + Py * (p0[2] + cz));
         const SubDesc& o = d.subs[s2];
-        const int ix = cx ? i1[0] : i0[0], iy = cy ? i1[1] : i0[1], iz = cz ? i1[2] : i0[2];
-        fn(o.off + ix + (int64_t)o.n[0] * (iy + (int64_t)o.n[1] * iz));
+        const int l0 = G[o.perm[0]] - o.lo[o.perm[0]], l1 = G[o.perm[1]] - o.lo[o.perm[1]];
+        const int l2 = G[o.perm[2]] - o.lo[o.perm[2]];
+        fn(o.off + l0 + (int64_t)o.n[0] * (l1 + (int64_t)o.n[1] * l2));
       }
   return nc[0] * nc[1] * nc[2];
 }
@@ -187,7 +195,9 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
       acc[1] = fs * fs;
       if (phi) {
         const int64_t nodes = (int64_t)d.geo.nn[0] * d.geo.nn[1] * d.geo.nn[2];
-        const int64_t g = (sd.lo[0] + i) + (int64_t)d.geo.nn[0] * ((sd.lo[1] + j) + (int64_t)d.geo.nn[1] * (sd.lo[2] + k));
+        int G[3];
+        global_node(sd, i, j, k, G);
+        const int64_t g = G[0] + (int64_t)d.geo.nn[0] * (G[1] + (int64_t)d.geo.nn[1] * G[2]);
         phi[sd.copy * nodes + g] = ut[sd.off + t];
       }
     }
@@ -248,13 +258,14 @@ __global__ void k_load_density(Dev d, const double* __restrict__ drho, double G,
   const int n = sd.n[0] * sd.n[1] * sd.n[2];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const int li[3] = {t % sd.n[0], (t / sd.n[0]) % sd.n[1], t / (sd.n[0] * sd.n[1])};
+  int gn[3];
+  global_node(sd, t % sd.n[0], (t / sd.n[0]) % sd.n[1], t / (sd.n[0] * sd.n[1]), gn);
   int el[3][2], ne[3];
   double w[3][2];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int gc = sd.lo[a] + li[a];
-    const int e0 = sd.e0[a], e1 = sd.e0[a] + sd.ne2[a] / 2;
+  for (int a = 0; a < 3; ++a) {  // global axis a
+    const int gc = gn[a];
+    const int e0 = sd.e0[a], e1 = sd.e0[a] + sd.ne2[sd.iperm[a]] / 2;
     const double h = d.geo.h[a];
     ne[a] = 0;
     if (gc & 1) {
@@ -294,7 +305,9 @@ __global__ void k_load_nodes(Dev d, const double* __restrict__ fn, double* __res
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if ((li[a] == 0 && sd.face[2 * a] >= 0) || (li[a] == sd.n[a] - 1 && sd.face[2 * a + 1] >= 0)) mult *= 2;
-  const int64_t g = (sd.lo[0] + li[0]) + (int64_t)d.geo.nn[0] * ((sd.lo[1] + li[1]) + (int64_t)d.geo.nn[1] * (sd.lo[2] + li[2]));
+  int G[3];
+  global_node(sd, li[0], li[1], li[2], G);
+  const int64_t g = G[0] + (int64_t)d.geo.nn[0] * (G[1] + (int64_t)d.geo.nn[1] * G[2]);
   f[sd.off + t] = fn[g] / double(mult);
 }
 

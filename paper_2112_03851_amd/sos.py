@@ -52,7 +52,7 @@ class Opts(C.Structure):
                 ("max_inner", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_tol", C.c_double), ("inner_abs", C.c_double), ("G", C.c_double),
                 ("stream", C.c_void_p), ("block", C.c_int32), ("team", C.c_int32), ("timing", C.c_int32),
-                ("wave_rows", C.c_int32), ("resident", C.c_int32)]
+                ("wave_rows", C.c_int32), ("resident", C.c_int32), ("march", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -123,6 +123,7 @@ def lib():
         "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_history": (C.c_int, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
         "sos_teams": (C.c_int, [P, C.POINTER(I)]),
+        "sos_axes": (C.c_int, [P, C.POINTER(I)]),
         "sos_set_teams": (C.c_int, [P, C.POINTER(I)]),
         "sos_residual_noalloc": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_debug_barrier": (C.c_int, [P, C.c_int64, I]),
@@ -297,8 +298,11 @@ class Problem:
         lo = (C.c_int32 * (3 * n))()
         foff = (C.c_int64 * (nf + 1))()
         _check(lib().sos_layout(self.h, C.byref(ns), off, dims, lo, foff))
+        perm = (C.c_int32 * (3 * n))()
+        _check(lib().sos_axes(self.h, perm))
         return {"offsets": np.array(off, np.int64), "dims": np.array(dims, np.int32).reshape(-1, 3),
-                "lo": np.array(lo, np.int32).reshape(-1, 3), "face_off": np.array(foff, np.int64)}
+                "lo": np.array(lo, np.int32).reshape(-1, 3), "face_off": np.array(foff, np.int64),
+                "perm": np.array(perm, np.int32).reshape(-1, 3)}
 
     def set_robin(self, p, q=0.0):
         self._robin = self._make_robin(self._per_face(p), self.n_faces, self._per_face(q))
@@ -410,6 +414,13 @@ class Problem:
         _sync_torch()
         _check(lib().sos_residual_noalloc(self.h, _ptr(phi) if phi is not None else None, C.byref(res)))
         return phi, res.value
+
+    def axes(self):
+        """Global axis of local axes 0, 1, 2 per subdomain (axis 2 is marched)."""
+        n = len(self.layout()["dims"])
+        out = (C.c_int32 * (3 * n))()
+        _check(lib().sos_axes(self.h, out))
+        return np.array(out, np.int32).reshape(-1, 3)
 
     def teams(self):
         """Team size of the fused CG kernel per subdomain."""

@@ -16,10 +16,11 @@ job (the oracle on the CPU, the HIP library on the GPU).
   c5copy  unit cube, 32^3 elements, 2x2x2 subdomains: the small copy on which
       candidate transmission conditions are scored before the c5 solve
   slab32 / slab64 / slab128  the shape of the paper's Sec. 6 runs: a
-      250 x 250 x 15 box (scaled to 1 x 1 x 0.06) cut into 32, 64 or 128
-      slabs along x, crater-like field with the thin axis vertical, tol 1e-6;
-      stored with the thin axis as y (320 x 19 x 320 elements, 16.0 M nodes)
-      so every slab's x-y node plane stays small. Robin coefficients: the
+      250 x 250 x 15 box (scaled to 1 x 1 x 0.06, 320 x 320 x 19 elements,
+      16.0 M nodes) cut into 32, 64 or 128 slabs along x, crater-like field
+      with the thin axis z vertical, tol 1e-6 (a slab's x-y node plane is
+      larger than a workgroup marches, so the solver marches it along y).
+      Robin coefficients: the
       second-order symmetric condition from the Fourier optimisation over the
       interface's frequency range (extra["kmin"], extra["kmax"])
 
@@ -130,8 +131,8 @@ def workload(name: str, seed: int = 0, **over) -> Workload:
                       density="crater", n_blobs=10)
     elif name in ("slab32", "slab64", "slab128"):
         parts = int(name[4:])
-        ne = (320, 19, 320)
-        lengths = (1.0, 0.06, 1.0)
+        ne = (320, 320, 19)
+        lengths = (1.0, 1.0, 0.06)
         widths = [320 // parts + (1 if k < 320 % parts else 0) for k in range(parts)]
         cuts = (tuple(int(v) for v in np.cumsum(widths)[:-1]), (), ())
         hy, hz = lengths[1] / ne[1], lengths[2] / ne[2]
@@ -140,7 +141,7 @@ def workload(name: str, seed: int = 0, **over) -> Workload:
         kmin = float(np.pi * np.hypot(1.0 / lengths[1], 1.0 / lengths[2]))
         kmax = float(np.pi * np.hypot(2.0 / hy, 2.0 / hz))
         wl = Workload(name, ne, lengths, dirichlet, cuts, 8.0 * ne[0], 1e-6, seed, density="crater", n_blobs=10,
-                      extra={"kmin": kmin, "kmax": kmax, "robin_kind": 2}, up=1)
+                      extra={"kmin": kmin, "kmax": kmax, "robin_kind": 2}, up=2)
     else:
         raise KeyError(name)
     for k, v in over.items():

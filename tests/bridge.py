@@ -37,7 +37,9 @@ class Case:
         lay = prob.layout()
         assert len(lay["dims"]) == self.part.n_sub
         for s, sub in enumerate(self.part.subs):
-            assert tuple(lay["dims"][s]) == sub.shape, (s, lay["dims"][s], sub.shape)
+            perm = lay["perm"][s]
+            assert sorted(perm.tolist()) == [0, 1, 2], perm
+            assert tuple(lay["dims"][s]) == tuple(sub.shape[g] for g in perm), (s, lay["dims"][s], sub.shape, perm)
             assert tuple(lay["lo"][s]) == sub.lo
         f = prob.faces()
         assert len(f) == len(self.part.faces)
@@ -45,16 +47,30 @@ class Case:
             assert tuple(a) == (b.s, b.j, b.axis, b.side)
         return lay
 
+    @staticmethod
+    def _axes(perm):
+        """numpy axes that take an (nz, ny, nx) array (x fastest) to the local
+        order (local axis 0 fastest): local axis a is global axis perm[a]."""
+        return [2 - int(perm[2]), 2 - int(perm[1]), 2 - int(perm[0])]
+
     def to_local(self, lay, parts, dtype=np.float64):
         out = np.zeros(int(lay["offsets"][-1]), dtype)
         for s, v in enumerate(parts):
+            sub = self.part.subs[s]
+            nx, ny, nz = sub.shape
+            v = np.transpose(np.asarray(v).reshape(nz, ny, nx), self._axes(lay["perm"][s])).ravel()
             o = int(lay["offsets"][s])
             out[o:o + v.size] = v
         return out
 
     def from_local(self, lay, vec):
-        return [np.asarray(vec[int(lay["offsets"][s]):int(lay["offsets"][s]) + sub.n])
-                for s, sub in enumerate(self.part.subs)]
+        out = []
+        for s, sub in enumerate(self.part.subs):
+            perm = lay["perm"][s]
+            o = int(lay["offsets"][s])
+            loc = np.asarray(vec[o:o + sub.n]).reshape(*[sub.shape[g] for g in perm[::-1]])
+            out.append(np.transpose(loc, np.argsort(self._axes(perm))).ravel())
+        return out
 
     def lam_to_faces(self, lay, lam):
         fo = lay["face_off"]

@@ -37,9 +37,9 @@ def test_crater_field_vertical_axis_is_a_relabelling():
 def test_slab_workloads_have_the_paper_shape():
     for parts in (32, 64, 128):
         wl = workload(f"slab{parts}")
-        assert wl.nparts == (parts, 1, 1) and wl.tol == 1e-6 and wl.up == 1
+        assert wl.nparts == (parts, 1, 1) and wl.tol == 1e-6 and wl.up == 2
         widths = np.diff([0, *wl.cuts[0], wl.ne[0]])
         assert widths.sum() == 320 and widths.max() - widths.min() <= 1
-        assert abs(wl.lengths[1] / wl.lengths[0] - 15.0 / 250.0) < 1e-12
-        assert wl.n_nodes == 641 * 39 * 641
+        assert abs(wl.lengths[2] / wl.lengths[0] - 15.0 / 250.0) < 1e-12 and wl.lengths[1] == wl.lengths[0]
+        assert wl.n_nodes == 641 * 641 * 39
         assert wl.extra["kmin"] < wl.extra["kmax"]

@@ -120,11 +120,16 @@ __global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restric
 
 // ---------------------------------------------------------------------------- glue and residual
 
+// Element a (0, 1, 2: a run-time value) of a three-element set, by selects:
+// indexing a private array with a run-time index would put it in scratch
+// memory.
+__device__ __forceinline__ int pick3(int a, int v0, int v1, int v2) { return a == 0 ? v0 : (a == 1 ? v1 : v2); }
+
 // Global node index (per global axis) of local node (i, j, k) of sd.
-__device__ __forceinline__ void global_node(const SubDesc& sd, int i, int j, int k, int (&G)[3]) {
-  const int li[3] = {i, j, k};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) G[sd.perm[a]] = sd.lo[sd.perm[a]] + li[a];
+__device__ __forceinline__ void global_node(const SubDesc& sd, int i, int j, int k, int& g0, int& g1, int& g2) {
+  g0 = sd.lo[0] + pick3(sd.iperm[0], i, j, k);
+  g1 = sd.lo[1] + pick3(sd.iperm[1], i, j, k);
+  g2 = sd.lo[2] + pick3(sd.iperm[2], i, j, k);
 }
 
 // Visit the subdomain copies of local node (i, j, k) of sd in ascending
@@ -134,19 +139,20 @@ __device__ __forceinline__ void global_node(const SubDesc& sd, int i, int j, int
 // follows from the global node through that subdomain's own axis order.
 template <class Fn>
 __device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i, int j, int k, Fn&& fn) {
-  const int li[3] = {i, j, k};
-  int G[3];
-  global_node(sd, i, j, k, G);
+  int g0, g1, g2;
+  global_node(sd, i, j, k, g0, g1, g2);
   int p0[3], nc[3];
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
     const int a = sd.iperm[g];
+    const int la = pick3(a, i, j, k), na = pick3(a, sd.n[0], sd.n[1], sd.n[2]);
+    const int flo = pick3(a, sd.face[0], sd.face[2], sd.face[4]), fhi = pick3(a, sd.face[1], sd.face[3], sd.face[5]);
     nc[g] = 1;
     p0[g] = sd.pidx[g];
-    if (li[a] == 0 && sd.face[2 * a] >= 0) {
+    if (la == 0 && flo >= 0) {
       nc[g] = 2;
       p0[g] = sd.pidx[g] - 1;
-    } else if (li[a] == sd.n[a] - 1 && sd.face[2 * a + 1] >= 0) {
+    } else if (la == na - 1 && fhi >= 0) {
       nc[g] = 2;
     }
   }
@@ -156,8 +162,10 @@ __device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i
       for (int cx = 0; cx < nc[0]; ++cx) {
         const int s2 = sd.sbase + (p0[0] + cx) + Px * ((p0[1] + cy) + Py * (p0[2] + cz));
         const SubDesc& o = d.subs[s2];
-        const int l0 = G[o.perm[0]] - o.lo[o.perm[0]], l1 = G[o.perm[1]] - o.lo[o.perm[1]];
-        const int l2 = G[o.perm[2]] - o.lo[o.perm[2]];
+        // the node's local coordinates in o: its global ones along o's axes
+        const int l0 = pick3(o.perm[0], g0 - o.lo[0], g1 - o.lo[1], g2 - o.lo[2]);
+        const int l1 = pick3(o.perm[1], g0 - o.lo[0], g1 - o.lo[1], g2 - o.lo[2]);
+        const int l2 = pick3(o.perm[2], g0 - o.lo[0], g1 - o.lo[1], g2 - o.lo[2]);
         fn(o.off + l0 + (int64_t)o.n[0] * (l1 + (int64_t)o.n[1] * l2));
       }
   return nc[0] * nc[1] * nc[2];
@@ -195,9 +203,9 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
       acc[1] = fs * fs;
       if (phi) {
         const int64_t nodes = (int64_t)d.geo.nn[0] * d.geo.nn[1] * d.geo.nn[2];
-        int G[3];
-        global_node(sd, i, j, k, G);
-        const int64_t g = G[0] + (int64_t)d.geo.nn[0] * (G[1] + (int64_t)d.geo.nn[1] * G[2]);
+        int g0, g1, g2;
+        global_node(sd, i, j, k, g0, g1, g2);
+        const int64_t g = g0 + (int64_t)d.geo.nn[0] * (g1 + (int64_t)d.geo.nn[1] * g2);
         phi[sd.copy * nodes + g] = ut[sd.off + t];
       }
     }
@@ -259,13 +267,13 @@ __global__ void k_load_density(Dev d, const double* __restrict__ drho, double G,
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   int gn[3];
-  global_node(sd, t % sd.n[0], (t / sd.n[0]) % sd.n[1], t / (sd.n[0] * sd.n[1]), gn);
+  global_node(sd, t % sd.n[0], (t / sd.n[0]) % sd.n[1], t / (sd.n[0] * sd.n[1]), gn[0], gn[1], gn[2]);
   int el[3][2], ne[3];
   double w[3][2];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {  // global axis a
     const int gc = gn[a];
-    const int e0 = sd.e0[a], e1 = sd.e0[a] + sd.ne2[sd.iperm[a]] / 2;
+    const int e0 = sd.e0[a], e1 = sd.e0[a] + pick3(sd.iperm[a], sd.ne2[0], sd.ne2[1], sd.ne2[2]) / 2;
     const double h = d.geo.h[a];
     ne[a] = 0;
     if (gc & 1) {
@@ -305,9 +313,9 @@ __global__ void k_load_nodes(Dev d, const double* __restrict__ fn, double* __res
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if ((li[a] == 0 && sd.face[2 * a] >= 0) || (li[a] == sd.n[a] - 1 && sd.face[2 * a + 1] >= 0)) mult *= 2;
-  int G[3];
-  global_node(sd, li[0], li[1], li[2], G);
-  const int64_t g = G[0] + (int64_t)d.geo.nn[0] * (G[1] + (int64_t)d.geo.nn[1] * G[2]);
+  int g0, g1, g2;
+  global_node(sd, li[0], li[1], li[2], g0, g1, g2);
+  const int64_t g = g0 + (int64_t)d.geo.nn[0] * (g1 + (int64_t)d.geo.nn[1] * g2);
   f[sd.off + t] = fn[g] / double(mult);
 }
 

@@ -137,6 +137,12 @@ typedef struct {
                           smallest node plane; 1, 2, 3: x, y, z for all.
                           The other two axes keep their global order; see
                           sos_axes                                         */
+  int32_t schedule;    /* 1 (default): with one block per subdomain, each
+                          launch of the fused CG kernel takes the subdomains
+                          in decreasing order of the work of their previous
+                          inner solve ((iterations + 1) x nodes), so long
+                          solves start first; 0: fixed order, largest
+                          subdomain first                                  */
 } sos_opts;
 
 typedef struct {
@@ -339,6 +345,11 @@ int sos_residual_noalloc(sos_ctx* ctx, double* phi_nodes, double* rel_residual);
  * memory, either may be NULL). SOS_LOG=1 in the environment also prints one
  * line per check on stderr. */
 int sos_history(const sos_ctx* ctx, int32_t cap, int32_t* n, int32_t* outer, double* res);
+/* Inner PCG iterations (Sec. 6) of every subdomain in the last outer
+ * iteration, subdomain order of sos_layout, copy after copy. *n receives the
+ * number of subdomains of all copies; the first min(cap, *n) counts are copied
+ * to iters (host memory, may be NULL). Synchronises the context's stream. */
+int sos_inner_iters(sos_ctx* ctx, int32_t cap, int32_t* n, int32_t* iters);
 /* Failure-handling tests: spin_ticks bounds the team barrier's wait (wall
  * clock ticks at 100 MHz; 0 restores the default, about 1.3 s); tag_skew = 1
  * makes every member wait for a tag no member writes, so each team barrier

@@ -206,6 +206,7 @@ int check_opts(const sos_opts* o) {
   if (o->wave_rows && !o->block) return fail(SOS_EINVAL, "opts.wave_rows needs opts.block");
   if (o->resident != 0 && o->resident != 1) return fail(SOS_EINVAL, "opts.resident must be 0 or 1");
   if (o->march < 0 || o->march > 3) return fail(SOS_EINVAL, "opts.march must be 0 (automatic), 1, 2 or 3");
+  if (o->schedule != 0 && o->schedule != 1) return fail(SOS_EINVAL, "opts.schedule must be 0 or 1");
   return SOS_OK;
 }
 
@@ -493,7 +494,7 @@ std::string tune_key(const sos_ctx* c) {
     for (int a = 0; a < 3; ++a) mix((uint64_t)s.n[a]);
   mix((uint64_t)c->subs.size());
   char buf[160];
-  snprintf(buf, sizeof buf, "gfx950|v2|%s|%016llx|tol%.3g|abs%.3g|max%d", c->fp32 ? "fp32" : "fp64",
+  snprintf(buf, sizeof buf, "gfx950|v3|%s|%016llx|tol%.3g|abs%.3g|max%d", c->fp32 ? "fp32" : "fp64",
            (unsigned long long)h, c->opts.inner_tol, c->opts.inner_abs, c->opts.max_inner);
   return buf;
 }
@@ -721,6 +722,12 @@ hipError_t copy_load_to_rhs(sos_ctx* c) {
 }
 
 // One outer iteration in the batched form; ev (optional) brackets the fused kernel.
+// With one block per subdomain, the fused kernel's next launch takes the
+// subdomains in decreasing order of the work of their last inner solve.
+bool schedule_by_work(const sos_ctx* c) {
+  return c->opts.schedule && c->fused_team <= 1 && c->fmap.size() == c->subs.size();
+}
+
 int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
   HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
@@ -728,6 +735,7 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
+  if (schedule_by_work(c)) HIPCHK(launch_order_blocks(c->dev, c->scal, c->d_fmap, st));
   HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
   return SOS_OK;
 }
@@ -1119,6 +1127,7 @@ int sos_opts_default(sos_opts* o, int32_t precision) {
   o->timing = 0;
   o->wave_rows = 0;
   o->resident = 1;
+  o->schedule = 1;
   return SOS_OK;
 }
 
@@ -1416,7 +1425,7 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
   if (o->stream && o->stream != c->stream) return fail(SOS_EINVAL, "the stream is fixed at setup");
   if (o->march != c->opts.march) return fail(SOS_EINVAL, "the march axes are fixed at setup");
   const int old_block = c->opts.block, old_team = c->opts.team, old_rows = c->opts.wave_rows,
-            old_res = c->opts.resident;
+            old_res = c->opts.resident, old_sched = c->opts.schedule;
   const double old_tol = c->opts.inner_tol, old_abs = c->opts.inner_abs;
   void* st = c->opts.stream;
   c->opts = *o;
@@ -1429,6 +1438,7 @@ int sos_set_opts(sos_ctx* c, const sos_opts* o) {
     if (rc) return rc;
     c->tuned = o->block != 0 && o->team != 0;
   }
+  if (o->schedule != old_sched) c->fmap_dirty = true;  // back to the fixed order
   invalidate_graph(c);
   return SOS_OK;
 }
@@ -1648,6 +1658,19 @@ int sos_history(const sos_ctx* c, int32_t cap, int32_t* n, int32_t* outer, doubl
     if (outer) outer[i] = c->hist_outer[i];
     if (res) res[i] = c->hist_res[i];
   }
+  return SOS_OK;
+}
+
+int sos_inner_iters(sos_ctx* c, int32_t cap, int32_t* n, int32_t* iters) {
+  if (!c || !n) return fail(SOS_EINVAL, "NULL argument");
+  if (cap < 0) return fail(SOS_EINVAL, "cap must be >= 0");
+  *n = (int32_t)c->subs.size();
+  const size_t m = std::min<size_t>((size_t)cap, c->subs.size());
+  if (m == 0 || !iters) return SOS_OK;
+  std::vector<CgScal> h(m);
+  HIPCHK(hipMemcpyAsync(h.data(), c->scal, m * sizeof(CgScal), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < m; ++i) iters[i] = h[i].iters;
   return SOS_OK;
 }
 

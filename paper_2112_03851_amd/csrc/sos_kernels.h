@@ -161,6 +161,9 @@ inline int exchange_rows(int max_na) {
   const int r = kExThreads / (max_na > 0 ? max_na : 1);
   return r < 1 ? 1 : (r > kExchangeRows ? kExchangeRows : r);
 }
+// Fused kernel block table (one block per subdomain) ordered by the work of
+// each subdomain's last inner solve, longest first.
+hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap, hipStream_t st);
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
                            double* lam, hipStream_t st);
 // Glue: utilde = average of copies (local layout).

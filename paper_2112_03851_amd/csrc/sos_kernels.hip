@@ -33,6 +33,82 @@ __global__ void k_cg_init(int n_sub, const int32_t* __restrict__ bfirst, const d
   scal[s] = c;
 }
 
+// ---------------------------------------------------------------------------- block order
+
+// Block table of the fused kernel with one block per subdomain: subdomains in
+// decreasing order of the work of their last inner solve, (iterations + 1) x
+// nodes, quantised to kOrderBins bins of equal width (equal bins in index
+// order). Blocks are dispatched in index order onto compute units as these free
+// up, so when the grid takes several rounds of resident blocks this is list
+// scheduling with the longest jobs first. One workgroup; a counting sort whose
+// ranks inside a chunk come from wave ballots.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = 64;
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgScal* __restrict__ scal,
+                                                                TeamSlot* __restrict__ fmap) {
+  constexpr int NW = kOrderThreads / 64;
+  __shared__ unsigned long long wmax[NW];
+  __shared__ int32_t base[kOrderBins];
+  __shared__ int32_t wcnt[NW][kOrderBins];
+  const int n = d.geo.n_sub;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  auto cost = [&](int s) -> unsigned long long {
+    const SubDesc& sd = d.subs[s];
+    const unsigned long long nodes = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
+    return (unsigned long long)(max(scal[s].iters, 0) + 1) * nodes;
+  };
+  unsigned long long m = 1;
+  for (int s = tid; s < n; s += kOrderThreads) m = max(m, cost(s));
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o, 64));
+  if (tid < kOrderBins) base[tid] = 0;
+  if (lane == 0) wmax[w] = m;
+  __syncthreads();
+  unsigned long long mx = 1;
+  for (int i = 0; i < NW; ++i) mx = max(mx, wmax[i]);
+  auto bin = [&](int s) { return kOrderBins - 1 - (int)(cost(s) * (kOrderBins - 1) / mx); };
+  for (int s = tid; s < n; s += kOrderThreads) atomicAdd(&base[bin(s)], 1);
+  __syncthreads();
+  if (tid == 0) {  // counts -> first position of each bin
+    int acc = 0;
+    for (int k = 0; k < kOrderBins; ++k) {
+      const int c = base[k];
+      base[k] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += kOrderThreads) {
+    const int s = c0 + tid;
+    const int k = s < n ? bin(s) : -1;
+    wcnt[w][lane] = 0;
+    __syncthreads();
+    // rank among the lanes of this wave with the same bin, and the wave's count per bin
+    int rank = 0;
+    unsigned long long todo = __ballot(k >= 0);
+    while (todo) {
+      const int kk = __shfl(k, __builtin_ctzll(todo), 64);
+      const unsigned long long same = __ballot(k == kk);
+      if (k == kk) rank = __popcll(same & ((1ull << lane) - 1ull));
+      if (lane == 0) wcnt[w][kk] = __popcll(same);
+      todo &= ~same;
+    }
+    __syncthreads();
+    if (tid < kOrderBins) {  // per bin: first position of each wave's lanes, then the next chunk's
+      int acc = base[tid];
+      for (int i = 0; i < NW; ++i) {
+        const int c = wcnt[i][tid];
+        wcnt[i][tid] = acc;
+        acc += c;
+      }
+      base[tid] = acc;
+    }
+    __syncthreads();
+    if (k >= 0) fmap[wcnt[w][k] + rank] = TeamSlot{s, 0, 1, 0};
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------- exchange
 
 // Position of face F's nodes in the concatenated local vectors: node (a, b)
@@ -452,6 +528,11 @@ hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threa
   if (a.res && (!fp32 || !a.zu || lds > a.lds_bytes)) return hipErrorInvalidValue;
   SOS_DISPATCH_CPT(cpt, return launch_fused_cpt<C>(d, L, fp32, threads, lds, a, st, plain));
   return hipSuccess;
+}
+
+hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap, hipStream_t st) {
+  hipLaunchKernelGGL(k_order_blocks, dim3(1), dim3(kOrderThreads), 0, st, d, scal, fmap);
+  return hipGetLastError();
 }
 
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,

@@ -52,7 +52,8 @@ class Opts(C.Structure):
                 ("max_inner", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_tol", C.c_double), ("inner_abs", C.c_double), ("G", C.c_double),
                 ("stream", C.c_void_p), ("block", C.c_int32), ("team", C.c_int32), ("timing", C.c_int32),
-                ("wave_rows", C.c_int32), ("resident", C.c_int32), ("march", C.c_int32)]
+                ("wave_rows", C.c_int32), ("resident", C.c_int32), ("march", C.c_int32),
+                ("schedule", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -122,6 +123,7 @@ def lib():
         "sos_iterate": (C.c_int, [P, I, C.POINTER(Stats)]),
         "sos_residual": (C.c_int, [P, P, C.POINTER(D)]),
         "sos_history": (C.c_int, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
+        "sos_inner_iters": (C.c_int, [P, I, C.POINTER(I), C.POINTER(I)]),
         "sos_teams": (C.c_int, [P, C.POINTER(I)]),
         "sos_axes": (C.c_int, [P, C.POINTER(I)]),
         "sos_set_teams": (C.c_int, [P, C.POINTER(I)]),
@@ -443,6 +445,15 @@ class Problem:
         res = (C.c_double * max(1, n.value))()
         _check(lib().sos_history(self.h, n.value, C.byref(n), outer, res))
         return [(int(outer[i]), float(res[i])) for i in range(n.value)]
+
+    def inner_iters(self):
+        """Inner PCG iterations of every subdomain (copy after copy) in the last
+        outer iteration."""
+        n = C.c_int32()
+        _check(lib().sos_inner_iters(self.h, 0, C.byref(n), None))
+        out = (C.c_int32 * max(1, n.value))()
+        _check(lib().sos_inner_iters(self.h, n.value, C.byref(n), out))
+        return [int(out[i]) for i in range(n.value)]
 
     def debug_barrier(self, spin_ticks=0, tag_skew=0):
         """Failure-handling tests: bound of the team barrier's wait (ticks at

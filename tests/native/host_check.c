@@ -64,6 +64,9 @@ int main(void) {
   ob = o;
   ob.team = 9;
   CHECK(setup_code(&m, &p, &r, &ob) == SOS_EINVAL);
+  ob = o;
+  ob.schedule = 2;
+  CHECK(setup_code(&m, &p, &r, &ob) == SOS_EINVAL);
   double pf[2] = {1.0, 0.0};
   sos_robin rpf = {0, 0.0, 0.0, pf, NULL};
   CHECK(setup_code(&m, &p, &rpf, &o) == SOS_EINVAL);          /* per-face p <= 0 */
@@ -82,6 +85,7 @@ int main(void) {
   int32_t n = -1;
   CHECK(sos_faces(NULL, &n, NULL) == SOS_EINVAL);
   CHECK(sos_history(NULL, 0, &n, NULL, NULL) == SOS_EINVAL);
+  CHECK(sos_inner_iters(NULL, 0, &n, NULL) == SOS_EINVAL);
   sos_destroy(NULL);
 
   /* CMA-ES on the two-subdomain Fourier factor, every kind */

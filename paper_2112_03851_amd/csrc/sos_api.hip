@@ -830,6 +830,17 @@ void history_reset(sos_ctx* c) {
   c->outer_total = 0;
 }
 
+// The fused kernel scales the previous direction vectors by beta = 0 in its
+// first CG iteration instead of selecting zero, so they must hold finite
+// values: cleared before every run of outer iterations and before tuning
+// (fresh allocations, or a run that broke down, may hold anything); every
+// launch that does not break down leaves them finite. Outside any graph.
+int zero_directions(sos_ctx* c) {
+  const size_t bytes = (size_t)c->n_local * (c->fp32 ? sizeof(float) : sizeof(double));
+  for (void* v : {c->p0, c->p1, c->s0, c->s1}) HIPCHK(hipMemsetAsync(v, 0, bytes, c->stream));
+  return SOS_OK;
+}
+
 // Runs outer iterations until the residual <= tol (tol <= 0: exactly max_outer
 // iterations with one check every check_every). Every check reads the global
 // residual and the solve's breakdown bits (one mapped host word each); a set
@@ -841,6 +852,10 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
   // cleared outside any graph (a captured memset node is avoided on purpose)
   HIPCHK(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), st));
   HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int32_t), st));
+  if (c->opts.mode == SOS_BATCHED) {
+    int rc = zero_directions(c);
+    if (rc) return rc;
+  }
   c->h_res[1] = 0.0;
   c->kernel_ms = 0.0;
   c->kernel_launches = 0;
@@ -1004,6 +1019,7 @@ int autotune(sos_ctx* c) {
     for (int t : {1, 2, 4, 8})
       if (team_ok(t, -1)) teams.push_back(t);
   hipStream_t st = c->stream;
+  if (int rc0 = zero_directions(c)) return rc0;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

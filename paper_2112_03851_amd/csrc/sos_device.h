@@ -1066,16 +1066,18 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
   // march planes: the second operand plane only with second-order terms or
   // wave-owned rows (see zmarch)
   const int mplanes = RES ? march_planes(Q, ra) : kPlanes;
-  lds_zero(lds, sl.G * mplanes * sl.SP);
+  // march planes, and the resident x (and p) of the first CG iteration where
+  // the launch's LDS holds them (else the block reports a launch mismatch)
+  const int res_words = (RES && ZU) ? (RES == 1 ? 2 : 1) * (zb1 - zb0) * sl.S : 0;
+  const bool res_fit = (size_t)(sl.G * mplanes * sl.SP + res_words) * sizeof(T) <= a.lds_bytes;
+  lds_zero(lds, sl.G * mplanes * sl.SP + (res_fit ? res_words : 0));
   __syncthreads();
   // resident p (RES 1) and x: one LDS value per own node, index li - S uz0
   T* const xres = lds + sl.G * mplanes * sl.SP;
   T* const pres = xres + (size_t)(zb1 - zb0) * sl.S;
   const uint32_t plane0 = (uint32_t)(sl.S * zb0);
   int t = 0, brk = 0;  // brk: BreakBits of this block
-  if (RES && (!ZU || (size_t)(sl.G * mplanes * sl.SP + (RES == 1 ? 2 : 1) * (zb1 - zb0) * sl.S) * sizeof(T) >
-                         a.lds_bytes))
-    brk |= kBrkLaunch;  // the host sizes the LDS for the largest z-range
+  if (RES && (!ZU || !res_fit)) brk |= kBrkLaunch;  // the host sizes the LDS for the largest z-range
   if (!COH && TM > 1) brk |= kBrkLaunch;  // the host picks the coherent variant whenever a team has 2+ blocks
   if (!isfinite(rr) || !isfinite(bb)) brk |= kBrkNonFinite;
   if (ZU && sl.G != 1) brk |= kBrkLaunch;  // the host selects ZU only when every block has one segment
@@ -1123,7 +1125,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
       T* __restrict__ sn_ = (odd ? s0b : s1b) + sl.off;
       T* __restrict__ pn_ = (odd ? p0b : p1b) + sl.off;
       const bool first = t == 0;
-      const T ta = T(alpha), tb = T(beta);
+      const T ta = T(alpha), tb = T(beta), rsc = first ? tsig : T(1);
       // per-thread partial sums in the inner precision (a few dozen terms),
       // combined across the block in FP64
       T ag = T(0), ad = T(0), ar = T(0);
@@ -1171,11 +1173,13 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
         }
       };
       auto make = [&](const auto& v, uint32_t li, bool own, bool, T dinv) {
-        // the first iteration has no previous direction and no iterate (the
-        // buffers may hold anything, so select rather than scale by zero)
-        const T vs = first ? T(0) : v.s;
-        const T vr = first ? v.r * tsig : v.r;  // r0 comes unscaled from the residual kernel
-        const T sn = v.w + tb * vs;
+        // the first iteration has no previous direction: beta = 0 there, and
+        // the direction buffers hold finite values (cleared before every run
+        // of outer iterations, finite after every launch that does not end
+        // the solve), so beta s and beta p vanish without a select; the
+        // resident x (and p) start at zero
+        const T vr = v.r * rsc;  // r0 comes unscaled from the residual kernel
+        const T sn = v.w + tb * v.s;
         const T rn = vr - ta * sn;
         const T un = dinv * rn;
         if constexpr (RES != 0) {
@@ -1183,13 +1187,13 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
             const uint32_t q = li - plane0;
             T pn;
             if constexpr (RES == 1) {
-              pn = fma(tb, first ? T(0) : pres[q], dinv * vr);
+              pn = fma(tb, pres[q], dinv * vr);
               pres[q] = pn;
             } else {
-              pn = fma(tb, first ? T(0) : v.p, dinv * vr);
+              pn = fma(tb, v.p, dinv * vr);
               at(pn_, li) = pn;
             }
-            xres[q] = fma(ta, pn, first ? T(0) : xres[q]);
+            xres[q] = fma(ta, pn, xres[q]);
             if constexpr (COH) {
               st_coh(&at(sn_, li), sn);
               st_coh(&at(rn_, li), rn);
@@ -1203,8 +1207,9 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_fused_cg(Dev d, const int
           return un;
         } else {
         // the same rounding as the resident form: explicit fused multiply-adds
-        const T vp = first ? T(0) : v.p, vx = first ? T(0) : v.x;
-        const T pn = fma(tb, vp, dinv * vr);
+        // (the global x still holds the last outer iteration's correction)
+        const T vx = first ? T(0) : v.x;
+        const T pn = fma(tb, v.p, dinv * vr);
         if (own) {
           if constexpr (COH) {
             st_coh(&at(pn_, li), pn);

@@ -114,7 +114,8 @@ struct sos_ctx {
   void *r1 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr;  // fused CG only
   double* part = nullptr;       // 3 per segmented block
   double* part_norm = nullptr;  // 2 per assemble block
-  int n_norm_blocks = 0;
+  int max_shell = 0;     // most shell nodes of a subdomain
+  int n_norm_blocks = 0;  // residual check partials: march blocks, then shell blocks
   double* d_res = nullptr;      // [res, r'r, f'f]
   double* psi = nullptr;        // adjoint field over all nodes (allocated on first use)
   CgScal* scal = nullptr;
@@ -664,14 +665,19 @@ hipError_t upload_expairs(sos_ctx* c) {
 
 // ------------------------------------------------------------------ outer iteration pieces
 
-int enqueue_check(sos_ctx* c, double* phi) {
+// The global residual check into the partials `part` (n_norm_blocks pairs)
+// with ut and rho (local layout) as its working vectors.
+int check_passes(sos_ctx* c, double* ut, double* rho, double* part, double* dres, double* phi) {
   hipStream_t st = c->stream;
-  HIPCHK(launch_glue(c->dev, c->max_n, c->u, c->ut, st));
-  HIPCHK(launch_local_residual(c->dev, c->seg.L, c->ut, c->f, c->rho, st));
-  HIPCHK(launch_assemble_norm(c->dev, c->max_n, c->rho, c->f, c->ut, phi, c->part_norm, st));
-  HIPCHK(launch_final_norm(c->part_norm, c->n_norm_blocks, c->geo.copies, c->flags, c->d_res, c->d_hres, st));
+  const int na = c->seg.L.nblocks;
+  HIPCHK(launch_glue_shell(c->dev, c->max_shell, c->u, ut, st));
+  HIPCHK(launch_check_residual(c->dev, c->seg.L, c->u, ut, c->f, rho, phi, part, st));
+  HIPCHK(launch_assemble_shell(c->dev, c->max_shell, rho, c->f, part + 2 * (size_t)na, st));
+  HIPCHK(launch_final_norm(part, na, c->n_norm_blocks - na, c->geo.copies, c->flags, dres, c->d_hres, st));
   return SOS_OK;
 }
+
+int enqueue_check(sos_ctx* c, double* phi) { return check_passes(c, c->ut, c->rho, c->part_norm, c->d_res, phi); }
 
 FusedArgs fused_args(sos_ctx* c) {
   FusedArgs a;
@@ -1352,7 +1358,8 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   // allocations
   const size_t es = c->fp32 ? 4 : 8;
   Dev tmp{nullptr, nullptr, g, 0, 0};
-  c->n_norm_blocks = assemble_blocks(tmp, c->max_n);
+  for (const SubDesc& d : c->subs) c->max_shell = std::max(c->max_shell, shell_nodes(d.n[0], d.n[1], d.n[2]));
+  c->n_norm_blocks = c->seg.L.nblocks + shell_blocks(tmp, c->max_shell);
   if ((rc = dalloc(&c->d_subs, c->subs.size())) || (rc = dalloc(&c->d_faces, c->faces.size())) ||
       (rc = dalloc(&c->d_expairs, c->pairs.size())) || (rc = dalloc(&c->d_fmap, c->fmap_cap)) ||
       (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
@@ -1408,7 +1415,6 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
   if (e == hipSuccess) e = hipMemset(c->b, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->u, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->lam, 0, std::max<int64_t>(1, c->n_lam) * sizeof(double));
-  if (e == hipSuccess) e = hipMemset(c->ut, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->rho, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->flags, 0, sizeof(int32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -1625,24 +1631,21 @@ int sos_residual(sos_ctx* c, double* phi, double* res) {
 int sos_residual_noalloc(sos_ctx* c, double* phi, double* res) {
   if (!c) return fail(SOS_EINVAL, "ctx is NULL");
   if (!c->scratch) return fail(SOS_ESTATE, "no scratch address for this context's device");
-  // ut and rho (local layout), the assemble partials and the result words
+  // ut and rho (local layout), the check partials and the result words
   const size_t n_vec = (size_t)align64(c->n_local);
   const size_t n_part = (size_t)align64(2 * (int64_t)c->n_norm_blocks);
   const size_t need = (2 * n_vec + n_part + 4 + (size_t)c->geo.copies) * sizeof(double);
   if (need > kScratchBytes)
     return fail(SOS_EINVAL, "the global residual of %lld local unknowns needs %zu bytes of scratch; the "
                 "allocation-free variant holds at most %zu bytes (about %zu local unknowns)",
-                (long long)c->n_local, need, kScratchBytes, kScratchBytes / (2 * sizeof(double)) - 4096);
+                (long long)c->n_local, need, kScratchBytes, kScratchBytes / (2 * sizeof(double)) - 8192);
   double* ut = static_cast<double*>(c->scratch);
   double* rho = ut + n_vec;
   double* part = rho + n_vec;
   double* dres = part + n_part;
   hipStream_t st = c->stream;
   if (phi) HIPCHK(launch_fill(phi, c->n_nodes, 0.0, st));
-  HIPCHK(launch_glue(c->dev, c->max_n, c->u, ut, st));
-  HIPCHK(launch_local_residual(c->dev, c->seg.L, ut, c->f, rho, st));
-  HIPCHK(launch_assemble_norm(c->dev, c->max_n, rho, c->f, ut, phi, part, st));
-  HIPCHK(launch_final_norm(part, c->n_norm_blocks, c->geo.copies, c->flags, dres, c->d_hres, st));
+  if (int rc = check_passes(c, ut, rho, part, dres, phi)) return rc;
   HIPCHK(hipStreamSynchronize(st));
   if (res) *res = c->h_res[0];
   return SOS_OK;

@@ -335,7 +335,6 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     if constexpr (ZU) return sl.uz1;
     else return sl.z1[m];
   };
-  using Raw = decltype(fetch(uint32_t(0), false));
   // coh: the plane lies outside the block's own z-range (another block of a
   // team writes it); edge: an own plane within two of the range's ends (the
   // neighbouring team members read it)
@@ -355,6 +354,16 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
     }
   };
   auto edge_of = [&](int k) { return k < sl.uz0 + 2 || k >= sl.uz1 - 2; };
+  // operand loads of slot m at plane kq: fetch(li, coh), or fetch(li, coh, i,
+  // j, kq) for a fetch that needs the node's local coordinates
+  auto fetch_at = [&](int m, int kq) {
+    const uint32_t li = uint32_t(sl.c[m] + sl.S * kq);
+    if constexpr (std::is_invocable_v<FetchF&, uint32_t, bool, int, int, int>)
+      return fetch(li, coh_of(kq), sl.i[m], sl.j[m], kq);
+    else
+      return fetch(li, coh_of(kq));
+  };
+  using Raw = decltype(fetch_at(0, 0));
   // first operand plane of the march: two below the segment, or (uniform z)
   // the subdomain's first plane when the segment starts there, since planes
   // outside the subdomain contribute nothing
@@ -388,7 +397,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       // unconditional load from a clamped, always valid plane: a fixed number
       // of loads per step lets every use wait for its own load only
       const int kq = min(max(kfirst(m) + q, 0), sl.nz - 1);
-      raw[m][q] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
+      raw[m][q] = fetch_at(m, kq);
     }
   }
   // the output of plane k is complete two steps after operand plane k + 2
@@ -416,7 +425,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       // a plane outside the subdomain is never stored, so its carry is unused
       pr[m][2] = T(carry_of(mv));
       const int kq = min(max(kp[m] + kPrefetch, 0), sl.nz - 1);
-      raw[m][U] = fetch(uint32_t(sl.c[m] + sl.S * kq), coh_of(kq));
+      raw[m][U] = fetch_at(m, kq);
     }
     // uniform z: the steps past the last needed plane only drain the
     // accumulator ring and touch no LDS, so they skip both barriers
@@ -669,29 +678,6 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
     part[3 * blockIdx.x + 1] = acc[1];
     part[3 * blockIdx.x + 2] = acc[2];
   }
-}
-
-// rho = f - K^N ut (Neumann local stiffness: no Robin terms).
-template <int CPT>
-__global__ void __launch_bounds__(Bound<CPT>::value) k_local_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ ut,
-                                                         const double* __restrict__ f, double* __restrict__ rho) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* lds = reinterpret_cast<double*>(smem);
-  const BlockDesc bd = blocks[blockIdx.x];
-  const SubDesc sd = d.subs[bd.s];
-  Slots<double, CPT, false> sl;
-  slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
-  lds_zero(lds, sl.G * kPlanes * sl.SP);
-  __syncthreads();
-  const double* __restrict__ utb = ut + sl.off;
-  const double* __restrict__ fb = f + sl.off;
-  double* __restrict__ rhob = rho + sl.off;
-  auto fetch = [=](uint32_t li, bool) { return at(utb, li); };
-  auto make = [](double v, uint32_t, bool, bool, double) { return v; };
-  auto store = [=](uint32_t li, bool en, bool, int, int, int, double q, double, double) {
-    if (en) at(rhob, li) = at(fb, li) - q;
-  };
-  zmarch(sl, lds, fetch, make, store);
 }
 
 // y = A x (diagnostic).

@@ -166,21 +166,30 @@ inline int exchange_rows(int max_na) {
 hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap, hipStream_t st);
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
                            double* lam, hipStream_t st);
-// Glue: utilde = average of copies (local layout).
-hipError_t launch_glue(const Dev& d, int max_n, const double* u, double* ut, hipStream_t st);
-// rho = f - K^N utilde (FP64, Neumann local stiffness).
-hipError_t launch_local_residual(const Dev& d, const SegLaunch& L, const double* ut, const double* f,
-                                 double* rho, hipStream_t st);
-// Owned nodes: r = sum of rho copies, f = sum of f copies, partial r'r, f'f;
-// phi (if not null) <- utilde on owned nodes.
-hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, const double* f,
-                                const double* ut, double* phi, double* part, hipStream_t st);
-// Number of partials (pairs) written by launch_assemble_norm.
-int assemble_blocks(const Dev& d, int max_n);
-// Per copy res_c = sqrt(sum rr / sum ff) -> dev_out[3 + c]; the largest over
-// the copies -> dev_out[0] and host_out[0] (host-mapped, may be null); the
-// solve's BreakBits (flags, may be null) -> host_out[1].
-hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, const int32_t* flags,
+// Global residual check. First pass: ut <- the average of each shell node's
+// copies (local layout; interior entries untouched).
+hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, double* ut, hipStream_t st);
+// Second pass (segmented launch L): rho = f - K^N u~ (FP64, local stiffness
+// without Robin terms), u~ = ut on the shell and u inside; interior nodes add
+// rho^2, f^2 to the block partials part[0 .. L.nblocks), shell nodes store
+// rho; phi (if not null) <- u~ on owned nodes.
+hipError_t launch_check_residual(const Dev& d, const SegLaunch& L, const double* u, const double* ut,
+                                 const double* f, double* rho, double* phi, double* part, hipStream_t st);
+// Shell nodes of a subdomain of n0 x n1 x n2 nodes (each at least 3): the
+// first and last planes, then the ring of each plane in between.
+__host__ __device__ inline int shell_nodes(int n0, int n1, int n2) {
+  return 2 * n0 * n1 + (n2 - 2) * (2 * (n0 + n1) - 4);
+}
+// Third pass: owned shell nodes, rho and f summed over copies; partials
+// part[0 .. shell_blocks(d, max_shell)).
+hipError_t launch_assemble_shell(const Dev& d, int max_shell, const double* rho, const double* f, double* part,
+                                 hipStream_t st);
+int shell_blocks(const Dev& d, int max_shell);
+// Per copy res_c = sqrt(sum rr / sum ff) over both passes' partials (na of the
+// first, then nb of the second) -> dev_out[3 + c]; the largest over the
+// copies -> dev_out[0] and host_out[0] (host-mapped, may be null); the solve's
+// BreakBits (flags, may be null) -> host_out[1].
+hipError_t launch_final_norm(const double* part, int32_t na, int32_t nb, int32_t copies, const int32_t* flags,
                              double* dev_out, double* host_out, hipStream_t st);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t st);
 // grad_e = 4 pi G sum_a psi_a int_e phi_a for every element (psi over all nodes).

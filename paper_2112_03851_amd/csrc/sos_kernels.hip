@@ -247,29 +247,124 @@ __device__ __forceinline__ int for_copies(const Dev& d, const SubDesc& sd, int i
   return nc[0] * nc[1] * nc[2];
 }
 
-__global__ void k_glue(Dev d, const double* __restrict__ u, double* __restrict__ ut) {
-  const SubDesc sd = d.subs[blockIdx.y];
-  const int n = sd.n[0] * sd.n[1] * sd.n[2];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int i = t % sd.n[0], j = (t / sd.n[0]) % sd.n[1], k = t / (sd.n[0] * sd.n[1]);
-  double s = 0.0;
-  const int n_c = for_copies(d, sd, i, j, k, [&](int64_t idx) { s += u[idx]; });
-  ut[sd.off + t] = s / double(n_c);
+// Global residual check (Sec. 6 stops on it) in three passes over the local
+// layout. Only nodes on a subdomain's shell have more than one copy.
+__device__ __forceinline__ bool on_shell(const SubDesc& sd, int i, int j, int k) {
+  return i == 0 || j == 0 || k == 0 || i == sd.n[0] - 1 || j == sd.n[1] - 1 || k == sd.n[2] - 1;
+}
+// A node on an interface belongs to the copy that is not at the lower end of
+// any interface.
+__device__ __forceinline__ bool owns_node(const SubDesc& sd, int i, int j, int k) {
+  return !((i == 0 && sd.face[0] >= 0) || (j == 0 && sd.face[2] >= 0) || (k == 0 && sd.face[4] >= 0));
+}
+// Shell node t of sd (t < shell_nodes): the first and last planes, then the
+// ring of each plane in between.
+__device__ __forceinline__ void shell_node(const SubDesc& sd, int t, int& i, int& j, int& k) {
+  const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2];
+  const int plane = nx * ny, ring = 2 * (nx + ny) - 4;
+  if (t < 2 * plane) {
+    k = t < plane ? 0 : nz - 1;
+    const int e = t < plane ? t : t - plane;
+    j = e / nx;
+    i = e - j * nx;
+  } else {
+    const int e = t - 2 * plane;
+    k = 1 + e / ring;
+    const int r = e - (k - 1) * ring;
+    if (r < nx) {
+      i = r;
+      j = 0;
+    } else if (r < 2 * nx) {
+      i = r - nx;
+      j = ny - 1;
+    } else {
+      const int r2 = r - 2 * nx;  // the two side columns, rows 1 .. ny-2
+      i = r2 < ny - 2 ? 0 : nx - 1;
+      j = 1 + (r2 < ny - 2 ? r2 : r2 - (ny - 2));
+    }
+  }
 }
 
-// A node is owned by the copy that is not at the lower end of any interface.
-__global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const double* __restrict__ f,
-                                const double* __restrict__ ut, double* __restrict__ phi,
-                                double* __restrict__ part) {
+// First pass: u~ (the average of the node's copies) at every shell node.
+__global__ void k_glue_shell(Dev d, const double* __restrict__ u, double* __restrict__ ut) {
   const SubDesc sd = d.subs[blockIdx.y];
-  const int n = sd.n[0] * sd.n[1] * sd.n[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= shell_nodes(sd.n[0], sd.n[1], sd.n[2])) return;
+  int i, j, k;
+  shell_node(sd, t, i, j, k);
+  double s = 0.0;
+  const int n = for_copies(d, sd, i, j, k, [&](int64_t idx) { s += u[idx]; });
+  ut[sd.off + i + (int64_t)sd.n[0] * (j + (int64_t)sd.n[1] * k)] = s / double(n);
+}
+
+// Second pass, the z-march of rho = f - K^N u~ (K^N: the local stiffness
+// without Robin terms), u~ read from the first pass on the shell and from u
+// inside. An interior node has one copy and is owned: its rho^2 and f^2 go
+// straight into the block's sums. A shell node's rho is stored for the third
+// pass, which sums the copies. The owner of each node writes u~ to phi when
+// phi is given.
+template <int CPT>
+__global__ void __launch_bounds__(Bound<CPT>::value)
+    k_check_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u, const double* __restrict__ ut,
+                     const double* __restrict__ f, double* __restrict__ rho, double* __restrict__ phi,
+                     double* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* lds = reinterpret_cast<double*>(smem);
+  const BlockDesc bd = blocks[blockIdx.x];
+  const SubDesc sd = d.subs[bd.s];
+  Slots<double, CPT, false> sl;
+  slots_init(sl, sd, d.geo, bd.z0, bd.z1, false);
+  lds_zero(lds, sl.G * kPlanes * sl.SP);
+  __syncthreads();
+  const double* __restrict__ ub = u + sl.off;
+  const double* __restrict__ utb = ut + sl.off;
+  const double* __restrict__ fb = f + sl.off;
+  double* __restrict__ rhob = rho + sl.off;
+  // plain scalars only in the functors (a descriptor captured whole would be
+  // kept in scratch memory)
+  const int nx1 = sd.n[0] - 1, ny1 = sd.n[1] - 1, nz1 = sd.n[2] - 1;
+  const bool fx = sd.face[0] >= 0, fy = sd.face[2] >= 0, fz = sd.face[4] >= 0;
+  auto shell = [=](int i, int j, int k) { return i == 0 || j == 0 || k == 0 || i == nx1 || j == ny1 || k == nz1; };
+  auto fetch = [=](uint32_t li, bool, int i, int j, int k) { return at(shell(i, j, k) ? utb : ub, li); };
+  auto make = [](double v, uint32_t, bool, bool, double) { return v; };
+  // phi index of local node (i, j, k): the global node through the axis order
+  const int64_t nn0 = d.geo.nn[0], nn01 = (int64_t)d.geo.nn[0] * d.geo.nn[1];
+  const int64_t pbase = sd.copy * nn01 * d.geo.nn[2] + sd.lo[0] + nn0 * sd.lo[1] + nn01 * sd.lo[2];
+  const int64_t st0 = sd.perm[0] == 0 ? 1 : (sd.perm[0] == 1 ? nn0 : nn01);
+  const int64_t st1 = sd.perm[1] == 0 ? 1 : (sd.perm[1] == 1 ? nn0 : nn01);
+  const int64_t st2 = sd.perm[2] == 0 ? 1 : (sd.perm[2] == 1 ? nn0 : nn01);
+  double arr = 0.0, aff = 0.0;
+  auto store = [&](uint32_t li, bool en, bool, int i, int j, int k, double q, double utv, double) {
+    if (!en) return;
+    const double fv = at(fb, li), rv = fv - q;
+    if (shell(i, j, k)) {
+      at(rhob, li) = rv;
+    } else {
+      arr += rv * rv;
+      aff += fv * fv;
+    }
+    if (phi && !((i == 0 && fx) || (j == 0 && fy) || (k == 0 && fz))) phi[pbase + i * st0 + j * st1 + k * st2] = utv;
+  };
+  zmarch(sl, lds, fetch, make, store);
+  double acc[2] = {arr, aff};
+  block_sum(acc);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = acc[0];
+    part[2 * blockIdx.x + 1] = acc[1];
+  }
+}
+
+// Third pass: the owned shell nodes of every subdomain, rho and f summed over
+// the node's copies and squared into the block's sums.
+__global__ void k_assemble_shell(Dev d, const double* __restrict__ rho, const double* __restrict__ f,
+                                 double* __restrict__ part) {
+  const SubDesc sd = d.subs[blockIdx.y];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[2] = {0.0, 0.0};
-  if (t < n) {
-    const int i = t % sd.n[0], j = (t / sd.n[0]) % sd.n[1], k = t / (sd.n[0] * sd.n[1]);
-    const bool owned = !((i == 0 && sd.face[0] >= 0) || (j == 0 && sd.face[2] >= 0) || (k == 0 && sd.face[4] >= 0));
-    if (owned) {
+  if (t < shell_nodes(sd.n[0], sd.n[1], sd.n[2])) {
+    int i, j, k;
+    shell_node(sd, t, i, j, k);
+    if (owns_node(sd, i, j, k)) {
       double rs = 0.0, fs = 0.0;
       for_copies(d, sd, i, j, k, [&](int64_t idx) {
         rs += rho[idx];
@@ -277,13 +372,6 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
       });
       acc[0] = rs * rs;
       acc[1] = fs * fs;
-      if (phi) {
-        const int64_t nodes = (int64_t)d.geo.nn[0] * d.geo.nn[1] * d.geo.nn[2];
-        int g0, g1, g2;
-        global_node(sd, i, j, k, g0, g1, g2);
-        const int64_t g = g0 + (int64_t)d.geo.nn[0] * (g1 + (int64_t)d.geo.nn[1] * g2);
-        phi[sd.copy * nodes + g] = ut[sd.off + t];
-      }
     }
   }
   block_sum(acc);
@@ -294,17 +382,22 @@ __global__ void k_assemble_norm(Dev d, const double* __restrict__ rho, const dou
   }
 }
 
-// Per copy (the assemble blocks of copy c are the contiguous range
-// [c nblk / copies, (c + 1) nblk / copies)): res_c = ||f - K u~|| / ||f||, and
-// the largest over the copies (the stopping quantity). dev_out: [max res,
+// Per copy: res_c = ||f - K u~|| / ||f|| from the sums of both passes (the
+// first pass's partials part[0 .. na), the second's part[na .. na + nb); the
+// blocks of copy c are the c-th of `copies` equal contiguous ranges of each),
+// and the largest over the copies (the stopping quantity). dev_out: [max res,
 // r'r, f'f of the worst copy, res_0 .. res_{copies-1}].
-__global__ void k_final_norm(const double* __restrict__ part, int nblk, int copies, const int32_t* flags,
+__global__ void k_final_norm(const double* __restrict__ part, int na, int nb, int copies, const int32_t* flags,
                              double* dev_out, double* host_out) {
-  const int per = nblk / copies;
+  const int pa = na / copies, pb = nb / copies;
   double worst = 0.0, wr = 0.0, wf = 0.0;
   for (int c = 0; c < copies; ++c) {
     double acc[2] = {0.0, 0.0};
-    for (int b = c * per + threadIdx.x; b < (c + 1) * per; b += blockDim.x) {
+    for (int b = c * pa + threadIdx.x; b < (c + 1) * pa; b += blockDim.x) {
+      acc[0] += part[2 * b];
+      acc[1] += part[2 * b + 1];
+    }
+    for (int b = na + c * pb + threadIdx.x; b < na + (c + 1) * pb; b += blockDim.x) {
       acc[0] += part[2 * b];
       acc[1] += part[2 * b + 1];
     }
@@ -545,30 +638,33 @@ hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na,
   return hipGetLastError();
 }
 
-hipError_t launch_glue(const Dev& d, int max_n, const double* u, double* ut, hipStream_t st) {
-  hipLaunchKernelGGL(k_glue, node_grid(d, max_n, 256), dim3(256), 0, st, d, u, ut);
+hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, double* ut, hipStream_t st) {
+  hipLaunchKernelGGL(k_glue_shell, node_grid(d, max_shell, kAssembleThreads), dim3(kAssembleThreads), 0, st, d, u,
+                     ut);
   return hipGetLastError();
 }
 
-hipError_t launch_local_residual(const Dev& d, const SegLaunch& L, const double* ut, const double* f, double* rho,
+hipError_t launch_check_residual(const Dev& d, const SegLaunch& L, const double* u, const double* ut,
+                                 const double* f, double* rho, double* phi, double* part, hipStream_t st) {
+  SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
+                                             d, L.blocks, u, ut, f, rho, phi, part));
+  return hipGetLastError();
+}
+
+int shell_blocks(const Dev& d, int max_shell) {
+  return ((max_shell + kAssembleThreads - 1) / kAssembleThreads) * d.geo.n_sub;
+}
+
+hipError_t launch_assemble_shell(const Dev& d, int max_shell, const double* rho, const double* f, double* part,
                                  hipStream_t st) {
-  SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_local_residual<C>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
-                                             d, L.blocks, ut, f, rho));
+  hipLaunchKernelGGL(k_assemble_shell, node_grid(d, max_shell, kAssembleThreads), dim3(kAssembleThreads), 0, st, d,
+                     rho, f, part);
   return hipGetLastError();
 }
 
-int assemble_blocks(const Dev& d, int max_n) { return ((max_n + kAssembleThreads - 1) / kAssembleThreads) * d.geo.n_sub; }
-
-hipError_t launch_assemble_norm(const Dev& d, int max_n, const double* rho, const double* f, const double* ut,
-                                double* phi, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_norm, node_grid(d, max_n, kAssembleThreads), dim3(kAssembleThreads), 0, st, d, rho,
-                     f, ut, phi, part);
-  return hipGetLastError();
-}
-
-hipError_t launch_final_norm(const double* part, int32_t nblk, int32_t copies, const int32_t* flags,
+hipError_t launch_final_norm(const double* part, int32_t na, int32_t nb, int32_t copies, const int32_t* flags,
                              double* dev_out, double* host_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, nblk, copies, flags, dev_out, host_out);
+  hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(1024), 0, st, part, na, nb, copies, flags, dev_out, host_out);
   return hipGetLastError();
 }
 

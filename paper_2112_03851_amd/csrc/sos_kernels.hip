@@ -58,15 +58,20 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
     const unsigned long long nodes = (unsigned long long)sd.n[0] * sd.n[1] * sd.n[2];
     return (unsigned long long)(max(scal[s].iters, 0) + 1) * nodes;
   };
-  unsigned long long m = 1;
-  for (int s = tid; s < n; s += kOrderThreads) m = max(m, cost(s));
+  // the first chunk's costs stay in registers (one subdomain per thread for
+  // up to kOrderThreads subdomains: each cost is read once)
+  const unsigned long long cost0 = tid < n ? cost(tid) : 0ull;
+  unsigned long long m = max(cost0, 1ull);
+  for (int s = tid + kOrderThreads; s < n; s += kOrderThreads) m = max(m, cost(s));
   for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o, 64));
   if (tid < kOrderBins) base[tid] = 0;
   if (lane == 0) wmax[w] = m;
   __syncthreads();
   unsigned long long mx = 1;
   for (int i = 0; i < NW; ++i) mx = max(mx, wmax[i]);
-  auto bin = [&](int s) { return kOrderBins - 1 - (int)(cost(s) * (kOrderBins - 1) / mx); };
+  const double bsc = double(kOrderBins - 1) / double(mx);
+  auto bin_of = [&](unsigned long long c) { return kOrderBins - 1 - min((int)(double(c) * bsc), kOrderBins - 1); };
+  auto bin = [&](int s) { return bin_of(s == tid ? cost0 : cost(s)); };
   for (int s = tid; s < n; s += kOrderThreads) atomicAdd(&base[bin(s)], 1);
   __syncthreads();
   if (tid == 0) {  // counts -> first position of each bin

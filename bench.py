@@ -295,6 +295,8 @@ def main():
         print(f"profiled {st['outer_iters']} outer iterations, {st['kernel_launches']} fused launches, "
               f"{st['kernel_bytes'] / st['kernel_launches']:.0f} algorithmic bytes per launch, "
               f"{st['kernel_ms'] / st['kernel_launches']:.4f} ms per launch", flush=True)
+        print("shape " + json.dumps({k: st[k] for k in ("block", "cols_per_thread", "team", "wave_rows", "resident")}),
+              flush=True)
         reference_copy(torch, args.profile_copy_mib)
         return
     every = args.check_every

@@ -995,6 +995,11 @@ int reset_state(sos_ctx* c) {
   return SOS_OK;
 }
 
+// A candidate replaces the tuner's best only when it is faster by more than
+// the launch-to-launch noise (1 %): the earliest of near-equal shapes wins, so
+// repeated tunings of one problem agree.
+constexpr double kTuneMargin = 0.99;
+
 // Autotuner: time every candidate block shape of the fused kernel with every
 // uniform team size on the first inner solve of the current load (u = 0,
 // lambda = 0), keep the fastest; then, for subdomains of uneven size (more
@@ -1063,7 +1068,7 @@ int autotune(sos_ctx* c) {
       if (cd.res && !fused_args(c).res) continue;  // p and x do not fit in LDS with this team
       double ms = INFINITY;
       if ((rc = time_config(&ms))) break;
-      if (ms < best) {
+      if (ms < best * kTuneMargin) {
         best = ms;
         bs = cd;
         bteams.assign(c->n_buckets, team);
@@ -1084,7 +1089,7 @@ int autotune(sos_ctx* c) {
         if (bs.res && !fused_args(c).res) continue;
         double ms = INFINITY;
         if ((rc = time_config(&ms))) break;
-        if (ms < best) {
+        if (ms < best * kTuneMargin) {
           best = ms;
           bteams = trial;
         }

@@ -175,9 +175,11 @@ hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, doubl
 // rho; phi (if not null) <- u~ on owned nodes.
 hipError_t launch_check_residual(const Dev& d, const SegLaunch& L, const double* u, const double* ut,
                                  const double* f, double* rho, double* phi, double* part, hipStream_t st);
-// Shell nodes of a subdomain of n0 x n1 x n2 nodes (each at least 3): the
-// first and last planes, then the ring of each plane in between.
+// Shell nodes of a subdomain of n0 x n1 x n2 nodes: with at least 3 along
+// every axis, the first and last planes, then the ring of each plane in
+// between; with at most 2 along some axis, every node.
 __host__ __device__ inline int shell_nodes(int n0, int n1, int n2) {
+  if (n0 <= 2 || n1 <= 2 || n2 <= 2) return n0 * n1 * n2;
   return 2 * n0 * n1 + (n2 - 2) * (2 * (n0 + n1) - 4);
 }
 // Third pass: owned shell nodes, rho and f summed over copies; partials

@@ -263,11 +263,16 @@ __device__ __forceinline__ bool owns_node(const SubDesc& sd, int i, int j, int k
   return !((i == 0 && sd.face[0] >= 0) || (j == 0 && sd.face[2] >= 0) || (k == 0 && sd.face[4] >= 0));
 }
 // Shell node t of sd (t < shell_nodes): the first and last planes, then the
-// ring of each plane in between.
+// ring of each plane in between (every node, in layout order, when some axis
+// has at most 2 nodes).
 __device__ __forceinline__ void shell_node(const SubDesc& sd, int t, int& i, int& j, int& k) {
   const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2];
   const int plane = nx * ny, ring = 2 * (nx + ny) - 4;
-  if (t < 2 * plane) {
+  if (nx <= 2 || ny <= 2 || nz <= 2) {
+    k = t / plane;
+    j = (t - k * plane) / nx;
+    i = t - k * plane - j * nx;
+  } else if (t < 2 * plane) {
     k = t < plane ? 0 : nz - 1;
     const int e = t < plane ? t : t - plane;
     j = e / nx;

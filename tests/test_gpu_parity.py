@@ -292,3 +292,33 @@ def test_second_order_fixed_point_and_fewer_iterations_than_zeroth_order():
         assert st["converged"] and err <= 1e-6
         res[q] = st["outer_iters"]
     assert res[0.02] < res[0.0]
+
+
+@pytest.mark.parametrize("name, ne, cuts", [
+    ("one_node_thick_z", (6, 5, 1), ((3,), (2,), ())),
+    ("one_node_thick_x", (1, 6, 5), ((), (3,), (2,))),
+    ("two_node_boundary_slab", (6, 5, 4), ((1, 4), (), (2,))),
+])
+def test_global_residual_on_subdomains_one_or_two_nodes_thick(name, ne, cuts):
+    """Subdomains with one or two kept nodes along an axis (every node on the
+    boundary shell): the reported global residual equals the oracle's residual
+    of the output at every check, and the solve reaches the direct solution."""
+    torch = _torch()
+    case = Case(ne, cuts=cuts, p=10.0 * max(ne))
+    drho = uniform_density(case.ne, seed=5)
+    f, _ = case.density_loads(drho)
+    ud = D.solve_direct(case.mesh, f, "lu")
+    for prec, mode, tol in (("fp64", "stepwise", 1e-12), ("fp32", "batched", 1e-11)):
+        prob = case.problem(precision=prec, mode=mode, max_outer=20000, inner_tol=1e-3, inner_abs=0.0)
+        prob.set_opts(max_outer=3)
+        phi, st = prob.solve(torch.tensor(drho, device="cuda"), 1e-30)
+        res_oracle = A.residual_norm(case.mesh, phi.cpu().numpy(), f)
+        print(name, prec, "after 3 outer: gpu", st["rel_residual"], "oracle", res_oracle, flush=True)
+        assert abs(st["rel_residual"] - res_oracle) <= 1e-9 * res_oracle
+        prob.set_opts(max_outer=20000)
+        phi, st = prob.solve(torch.tensor(drho, device="cuda"), tol)
+        err = np.abs(phi.cpu().numpy() - ud).max() / np.abs(ud).max()
+        res_oracle = A.residual_norm(case.mesh, phi.cpu().numpy(), f)
+        print(name, prec, mode, st["outer_iters"], "err", err, "residual", st["rel_residual"], res_oracle, flush=True)
+        assert st["converged"] and err <= 1e-10 and res_oracle <= tol * 1.001
+        prob.close()

@@ -165,29 +165,29 @@ constexpr int kMaxCopies = 4096;   // independent problem copies of one context
 
 void release(sos_ctx* c) {
   if (!c) return;
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  for (auto e : c->gevents) hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (auto e : c->gevents) (void)hipEventDestroy(e);
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_expairs, c->d_fmap, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_part,
                   c->scal, c->ndone, c->counters, c->flags};
   for (void* p : ptrs)
-    if (p) hipFree(p);
-  if (c->h_res) hipHostFree(c->h_res);
-  if (c->h_ndone) hipHostFree(c->h_ndone);
-  if (c->h_counters) hipHostFree(c->h_counters);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    if (p) (void)hipFree(p);
+  if (c->h_res) (void)hipHostFree(c->h_res);
+  if (c->h_ndone) (void)hipHostFree(c->h_ndone);
+  if (c->h_counters) (void)hipHostFree(c->h_counters);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
 void invalidate_graph(sos_ctx* c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   c->gexec = nullptr;
   c->graph = nullptr;
   c->graph_k = 0;
-  for (auto e : c->gevents) hipEventDestroy(e);
+  for (auto e : c->gevents) (void)hipEventDestroy(e);
   c->gevents.clear();
 }
 
@@ -783,8 +783,8 @@ int stepwise_iteration(sos_ctx* c) {
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     c->kernel_ms += ms;
     c->kernel_launches += launches;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
   HIPCHK(launch_add_correction(c->dev, L, c->fp32, c->u, c->x, c->scal, st));
   HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
@@ -801,7 +801,7 @@ int build_graph(sos_ctx* c, int k) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (rc != SOS_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return fail(SOS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -931,7 +931,7 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
         c->kernel_ms += ms;
         c->kernel_launches += 1;
       }
-      for (auto e : evs) hipEventDestroy(e);
+      for (auto e : evs) (void)hipEventDestroy(e);
       evs.clear();
     }
     done += k;
@@ -1096,8 +1096,8 @@ int autotune(sos_ctx* c) {
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1720,7 +1720,7 @@ int sos_apply_local(sos_ctx* c, int32_t precision, const void* x, void* y) {
 
 void sos_destroy(sos_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   release(c);
 }
 

@@ -762,7 +762,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
   const int s = bd.s;
   if (scal[s].done) return;
   const int b0 = bfirst[s], b1 = bfirst[s + 1];
-  const bool leader = (blockIdx.x == b0) && (threadIdx.x == 0);
+  const bool leader = ((int)blockIdx.x == b0) && (threadIdx.x == 0);
   double rz, rr;
   if (t == 0) {
     rz = scal[s].rz[0];
@@ -833,7 +833,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_update(Dev d, const Bl
   double pq = 0.0;
   for (int b = b0; b < b1; ++b) pq += part[3 * b];
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == b0 && threadIdx.x == 0) {
+    if ((int)blockIdx.x == b0 && threadIdx.x == 0) {
       const int32_t why = isfinite(pq) ? kBrkCurvature : kBrkNonFinite;
       scal[s].done = 1;
       scal[s].iters = t;
@@ -953,7 +953,7 @@ __device__ __forceinline__ void team_sum(double (&v)[N], const FusedArgs& a, int
 #pragma unroll
     for (int n = 0; n < N; ++n) st_coh(&slot[n], with_tag(v[n], tag));
   }
-  if (threadIdx.x < TM * N) {
+  if ((int)threadIdx.x < TM * N) {
     const int m = threadIdx.x / N, n = threadIdx.x - m * N;
     const double* q = base + ((size_t)m * 2 + (epoch & 1)) * kTeamSlot + n;
     double val = ld_coh(q);

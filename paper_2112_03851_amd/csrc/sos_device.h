@@ -657,8 +657,13 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   const double* __restrict__ ub = u + sl.off;
   const double* __restrict__ bb = b + sl.off;
   TO* __restrict__ rb = r + sl.off;
-  auto fetch = [=](uint32_t li, bool) { return Pair<double>{at(ub, li), at(bb, li)}; };
-  auto make = [](const Pair<double>& v, uint32_t, bool, bool, double) { return OpCarry<double>{v.a, v.b}; };
+  // u is prefetched with the operand ring; b is loaded when its plane's
+  // operand is made and carried to the store two steps later (were it part
+  // of the ring, its register would stay live after its reload is issued and
+  // the register allocator would copy every reloaded entry at the loop's end,
+  // waiting for all loads in flight)
+  auto fetch = [=](uint32_t li, bool) { return at(ub, li); };
+  auto make = [=](double v, uint32_t li, bool, bool, double) { return OpCarry<double>{v, at(bb, li)}; };
   auto store = [&](uint32_t li, bool en, bool, int, int, int, double q, double bv, double dinv) {
     if (!en) return;
     const TO rt = TO(bv - q);

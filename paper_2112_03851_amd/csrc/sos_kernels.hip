@@ -313,7 +313,7 @@ __global__ void k_glue_shell(Dev d, const double* __restrict__ u, double* __rest
 // straight into the block's sums. A shell node's rho is stored for the third
 // pass, which sums the copies. The owner of each node writes u~ to phi when
 // phi is given.
-template <int CPT>
+template <int CPT, bool PHI>
 __global__ void __launch_bounds__(Bound<CPT>::value)
     k_check_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u, const double* __restrict__ ut,
                      const double* __restrict__ f, double* __restrict__ rho, double* __restrict__ phi,
@@ -335,8 +335,11 @@ __global__ void __launch_bounds__(Bound<CPT>::value)
   const int nx1 = sd.n[0] - 1, ny1 = sd.n[1] - 1, nz1 = sd.n[2] - 1;
   const bool fx = sd.face[0] >= 0, fy = sd.face[2] >= 0, fz = sd.face[4] >= 0;
   auto shell = [=](int i, int j, int k) { return i == 0 || j == 0 || k == 0 || i == nx1 || j == ny1 || k == nz1; };
+  // the operand u~ is prefetched with the ring; f is loaded when its plane's
+  // operand is made and carried to the store two steps later (a load in the
+  // store itself would wait for every load in flight)
   auto fetch = [=](uint32_t li, bool, int i, int j, int k) { return at(shell(i, j, k) ? utb : ub, li); };
-  auto make = [](double v, uint32_t, bool, bool, double) { return v; };
+  auto make = [=](double v, uint32_t li, bool, bool, double) { return OpCarry<double>{v, at(fb, li)}; };
   // phi index of local node (i, j, k): the global node through the axis order
   const int64_t nn0 = d.geo.nn[0], nn01 = (int64_t)d.geo.nn[0] * d.geo.nn[1];
   const int64_t pbase = sd.copy * nn01 * d.geo.nn[2] + sd.lo[0] + nn0 * sd.lo[1] + nn01 * sd.lo[2];
@@ -344,16 +347,21 @@ __global__ void __launch_bounds__(Bound<CPT>::value)
   const int64_t st1 = sd.perm[1] == 0 ? 1 : (sd.perm[1] == 1 ? nn0 : nn01);
   const int64_t st2 = sd.perm[2] == 0 ? 1 : (sd.perm[2] == 1 ? nn0 : nn01);
   double arr = 0.0, aff = 0.0;
-  auto store = [&](uint32_t li, bool en, bool, int i, int j, int k, double q, double utv, double) {
+  auto store = [&](uint32_t li, bool en, bool, int i, int j, int k, double q, double fv, double) {
     if (!en) return;
-    const double fv = at(fb, li), rv = fv - q;
-    if (shell(i, j, k)) {
+    const double rv = fv - q;
+    const bool sh = shell(i, j, k);
+    if (sh) {
       at(rhob, li) = rv;
     } else {
       arr += rv * rv;
       aff += fv * fv;
     }
-    if (phi && !((i == 0 && fx) || (j == 0 && fy) || (k == 0 && fz))) phi[pbase + i * st0 + j * st1 + k * st2] = utv;
+    // the glued solution, when asked for (once per solve): u~ read again
+    if constexpr (PHI) {
+      if (!((i == 0 && fx) || (j == 0 && fy) || (k == 0 && fz)))
+        phi[pbase + i * st0 + j * st1 + k * st2] = at(sh ? utb : ub, li);
+    }
   };
   zmarch(sl, lds, fetch, make, store);
   double acc[2] = {arr, aff};
@@ -656,8 +664,13 @@ hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, doubl
 
 hipError_t launch_check_residual(const Dev& d, const SegLaunch& L, const double* u, const double* ut,
                                  const double* f, double* rho, double* phi, double* part, hipStream_t st) {
-  SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C>), dim3(L.nblocks), dim3(L.threads), L.lds64, st,
-                                             d, L.blocks, u, ut, f, rho, phi, part));
+  if (phi) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C, true>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+                                               st, d, L.blocks, u, ut, f, rho, phi, part));
+  } else {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C, false>), dim3(L.nblocks), dim3(L.threads), L.lds64,
+                                               st, d, L.blocks, u, ut, f, rho, phi, part));
+  }
   return hipGetLastError();
 }
 

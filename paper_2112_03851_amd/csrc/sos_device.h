@@ -754,7 +754,7 @@ __device__ __forceinline__ void cg_pass_b(const Slots<T, CPT, Q>& sl, bool first
 // ---------------------------------------------------------------------------- stepwise CG
 
 
-template <typename T, int CPT, bool Q>
+template <typename T, int CPT, bool Q, bool ZU = false>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const BlockDesc* blocks, const int32_t* __restrict__ bfirst,
                                                    int t, int max_inner, const T* __restrict__ r,
                                                    const T* __restrict__ pold, T* __restrict__ pnew,
@@ -819,9 +819,13 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_cg_apply(Dev d, const Blo
     at(qb, li) = qv;
     a0 += double(pk) * double(qv);
   };
-  zmarch(sl, lds, fetch, make, store);
+  // ZU: the host launches it only when every block marches one segment;
+  // otherwise the NaN partial ends the solve with a breakdown
+  const bool badseg = ZU && sl.G != 1;
+  if (!badseg) zmarch<ZU>(sl, lds, fetch, make, store);
   double acc[1] = {a0};
   block_sum(acc);
+  if (badseg) acc[0] = __builtin_nan("");
   if (threadIdx.x == 0) part[3 * blockIdx.x] = acc[0];
 }
 

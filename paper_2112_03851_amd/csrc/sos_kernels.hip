@@ -312,8 +312,9 @@ __global__ void k_glue_shell(Dev d, const double* __restrict__ u, double* __rest
 // inside. An interior node has one copy and is owned: its rho^2 and f^2 go
 // straight into the block's sums. A shell node's rho is stored for the third
 // pass, which sums the copies. The owner of each node writes u~ to phi when
-// phi is given.
-template <int CPT, bool PHI>
+// phi is given. ZU: every block marches one segment (the host checks;
+// otherwise the partials are NaN and the check reports a breakdown).
+template <int CPT, bool PHI, bool ZU = false>
 __global__ void __launch_bounds__(Bound<CPT>::value)
     k_check_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u, const double* __restrict__ ut,
                      const double* __restrict__ f, double* __restrict__ rho, double* __restrict__ phi,
@@ -363,9 +364,11 @@ __global__ void __launch_bounds__(Bound<CPT>::value)
         phi[pbase + i * st0 + j * st1 + k * st2] = at(sh ? utb : ub, li);
     }
   };
-  zmarch(sl, lds, fetch, make, store);
+  const bool badseg = ZU && sl.G != 1;
+  if (!badseg) zmarch<ZU>(sl, lds, fetch, make, store);
   double acc[2] = {arr, aff};
   block_sum(acc);
+  if (badseg) acc[0] = acc[1] = __builtin_nan("");
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = acc[0];
     part[2 * blockIdx.x + 1] = acc[1];
@@ -557,7 +560,11 @@ hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, 
                            const double* lam, double* b, void* r_out, double* part, double* team_part,
                            hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
-  if (fp32 && rz) {
+  if (fp32 && rz && L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true, true>), dim3(L.nblocks),
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out,
+                                               part, team_part));
+  } else if (fp32 && rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
                                                L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part, team_part));
   } else if (fp32 && L.zu) {
@@ -567,6 +574,10 @@ hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, 
   } else if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
                                                L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part, team_part));
+  } else if (rz && L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true, true>), dim3(L.nblocks),
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b,
+                                               (double*)r_out, part, team_part));
   } else if (rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
                                                L.lds64, st, d, L.blocks, u, f, lam, b, (double*)r_out, part, team_part));
@@ -590,11 +601,21 @@ hipError_t launch_cg_apply(const Dev& d, const SegLaunch& L, int fp32, int t, in
                            const void* p_old, void* p_new, void* q, double* part, CgScal* scal, int32_t* ndone,
                            unsigned long long* counters, int32_t* flags, hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
-  if (fp32) {
+  if (fp32 && L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds32, st, d, L.blocks, L.bfirst, t, max_inner, (const float*)r,
+                                               (const float*)p_old, (float*)p_new, (float*)q, part, scal, ndone,
+                                               counters, flags));
+  } else if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<float, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds32,
                                                st, d, L.blocks, L.bfirst, t, max_inner, (const float*)r,
                                                (const float*)p_old, (float*)p_new, (float*)q, part, scal, ndone,
                                                counters, flags));
+  } else if (L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<double, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, L.bfirst, t, max_inner, (const double*)r,
+                                               (const double*)p_old, (double*)p_new, (double*)q, part, scal,
+                                               ndone, counters, flags));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_cg_apply<double, C, Q>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, L.bfirst, t, max_inner, (const double*)r,
@@ -664,9 +685,15 @@ hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, doubl
 
 hipError_t launch_check_residual(const Dev& d, const SegLaunch& L, const double* u, const double* ut,
                                  const double* f, double* rho, double* phi, double* part, hipStream_t st) {
-  if (phi) {
+  if (phi && L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C, true, true>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, u, ut, f, rho, phi, part));
+  } else if (phi) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C, true>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, u, ut, f, rho, phi, part));
+  } else if (L.zu) {
+    SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C, false, true>), dim3(L.nblocks), dim3(L.threads),
+                                               L.lds64, st, d, L.blocks, u, ut, f, rho, phi, part));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_check_residual<C, false>), dim3(L.nblocks), dim3(L.threads), L.lds64,
                                                st, d, L.blocks, u, ut, f, rho, phi, part));

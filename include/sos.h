@@ -114,7 +114,9 @@ typedef struct {
                           batched solve times the candidate block shapes of
                           the fused kernel and keeps the fastest, cached in
                           $SOS_TUNE_CACHE (default ~/.cache/sos_autotune.jsonl)
-                          per subdomain geometry, precision and inner tolerance */
+                          per subdomain geometry, precision and inner tolerance
+                          (only when block and team are both 0: a search with
+                          either fixed neither reads nor writes the cache)   */
   int32_t team;        /* SOS_BATCHED blocks per subdomain in the fused kernel
                           (1..8; each owns a z-range, one team barrier per CG
                           iteration); 0 = autotune (with block)              */

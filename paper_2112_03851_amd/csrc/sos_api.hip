@@ -1010,9 +1010,12 @@ int autotune(sos_ctx* c) {
   if (c->tuned) return SOS_OK;
   c->tuned = true;
   const std::string key = tune_key(c);
+  // a block shape or team size fixed by the caller is kept: such a partial
+  // search neither reads nor writes the cache (its entries hold full searches)
+  const bool partial = c->opts.block != 0 || c->opts.team != 0;
   int th = 0, cp = 0, ra = 0, res = 0;
   std::vector<int32_t> bt;
-  if (tune_lookup(key, &th, &cp, &bt, &ra, &res) && (int)bt.size() == c->n_buckets &&
+  if (!partial && tune_lookup(key, &th, &cp, &bt, &ra, &res) && (int)bt.size() == c->n_buckets &&
       fused_shape(c, th, cp, ra, res && c->opts.resident) == SOS_OK && set_bucket_teams(c, bt) == SOS_OK)
     return SOS_OK;
   // block shapes are tuned unless fixed by opts.block, team sizes unless fixed by opts.team
@@ -1106,7 +1109,7 @@ int autotune(sos_ctx* c) {
   if (rc) return rc;
   c->tune_ms = best;
   invalidate_graph(c);
-  tune_store(key, bs.threads, bs.cpt, bteams, bs.ra, bs.res, best);
+  if (!partial) tune_store(key, bs.threads, bs.cpt, bteams, bs.ra, bs.res, best);
   return SOS_OK;
 }
 

@@ -85,3 +85,30 @@ def test_set_teams_rejects_teams_beyond_a_subdomains_planes():
     with pytest.raises(sos.SosError):
         prob.set_teams([0, 1, 1, 1])
     prob.close()
+
+
+def test_fixed_block_or_team_is_kept_over_a_cached_tuning(tmp_path, monkeypatch):
+    import torch
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SOS_TUNE_CACHE", str(cache))
+    case = Case(**UNEVEN)
+    drho = torch.tensor(uniform_density(case.ne, seed=9), device="cuda")
+    prob = case.problem(precision="fp32", mode="batched", check_every=10)
+    _, st = prob.solve(drho, 1e-8)
+    prob.close()
+    auto = st["block"]
+    assert st["converged"] and len(cache.read_text().splitlines()) == 1
+    # a fixed block shape (teams tuned) and a fixed team size (shape tuned)
+    # are kept although the cache holds a full search of the same geometry
+    fixed = 320 if auto != 320 else 384
+    prob = case.problem(precision="fp32", mode="batched", check_every=10, block=fixed)
+    _, st = prob.solve(drho, 1e-8)
+    prob.close()
+    print("cached block", auto, "fixed", fixed, "got", st["block"], flush=True)
+    assert st["converged"] and st["block"] == fixed
+    prob = case.problem(precision="fp32", mode="batched", check_every=10, team=2)
+    _, st = prob.solve(drho, 1e-8)
+    teams = prob.teams()
+    prob.close()
+    assert st["converged"] and np.all(teams == 2)
+    assert len(cache.read_text().splitlines()) == 1

@@ -23,6 +23,9 @@ APPLY_CASES = {
     "mixed_bc_ragged": dict(ne=(7, 6, 5), lengths=(1.0, 0.8, 1.3), bc=(0, 1, 0, 0, 1, 0),
                             cuts=((2, 3), (4,), (1,)), p=5.5),
     "plane_33x33": dict(ne=(48, 48, 3), cuts=((16, 32), (16, 32), ()), p=384.0),
+    # 64 x 64 = 4096 kept nodes per x-y plane: the largest plane a march takes
+    # (four columns per thread, 1024 threads)
+    "plane_64x64_max": dict(ne=(64, 64, 2), cuts=((32,), (32,), ()), p=512.0),
     "thin_columns": dict(ne=(12, 10, 20), lengths=(1.0, 1.0, 1.0), cuts=((2, 5, 9), (3, 7), ()), p=96.0),
     "single": dict(ne=(5, 4, 3), cuts=((), (), ()), p=1.0),
 }
@@ -322,3 +325,30 @@ def test_global_residual_on_subdomains_one_or_two_nodes_thick(name, ne, cuts):
         print(name, prec, mode, st["outer_iters"], "err", err, "residual", st["rel_residual"], res_oracle, flush=True)
         assert st["converged"] and err <= 1e-10 and res_oracle <= tol * 1.001
         prob.close()
+
+
+def test_largest_plane_solves_match_direct():
+    """Subdomains whose x-y plane has the largest supported node count (64 x
+    64 = 4096: four columns per thread in every kernel): the stepwise FP64 and
+    the batched FP32 solves reach the direct solution."""
+    torch = _torch()
+    case = Case((64, 64, 4), cuts=((32,), (32,), ()), p=512.0)
+    assert max(s.n for s in case.part.subs) == 64 * 64 * 7
+    drho = uniform_density(case.ne, seed=6)
+    f, _ = case.density_loads(drho)
+    ud = D.solve_direct(case.mesh, f, "lu")
+    for prec, mode, tol in (("fp64", "stepwise", 1e-11), ("fp32", "batched", 1e-11)):
+        prob = case.problem(precision=prec, mode=mode, max_outer=20000, inner_tol=1e-3, inner_abs=0.0,
+                            check_every=5)
+        phi, st = prob.solve(torch.tensor(drho, device="cuda"), tol)
+        prob.close()
+        phi = phi.cpu().numpy()
+        err = np.abs(phi - ud).max() / np.abs(ud).max()
+        res = A.residual_norm(case.mesh, phi, f)
+        print(prec, mode, "outer", st["outer_iters"], "block", st["block"], "x", st["cols_per_thread"],
+              "err", err, "residual", st["rel_residual"], res, flush=True)
+        # on this mesh (65 nodes a side) the relative error of an iterate is
+        # about 12 times its relative residual (fp64: 1.1e-10 at 9.6e-12)
+        assert st["converged"] and res <= tol * 1.001 and err <= 20 * tol
+        if mode == "batched":
+            assert st["cols_per_thread"] == 4 and st["block"] == 1024

@@ -741,8 +741,10 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
-  if (schedule_by_work(c)) HIPCHK(launch_order_blocks(c->dev, c->scal, c->d_fmap, st));
-  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
+  // the block ordering runs inside the exchange launch (one more workgroup)
+  const bool order = schedule_by_work(c);
+  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st,
+                         order ? &c->dev : nullptr, order ? c->scal : nullptr, order ? c->d_fmap : nullptr));
   return SOS_OK;
 }
 

@@ -164,8 +164,11 @@ inline int exchange_rows(int max_na) {
 // Fused kernel block table (one block per subdomain) ordered by the work of
 // each subdomain's last inner solve, longest first.
 hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap, hipStream_t st);
+// Robin exchange of every interface pair; with fmap (and d, scal) given, the
+// block ordering of launch_order_blocks runs as one more workgroup of it.
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
-                           double* lam, hipStream_t st);
+                           double* lam, hipStream_t st, const Dev* d = nullptr, const CgScal* scal = nullptr,
+                           TeamSlot* fmap = nullptr);
 // Global residual check. First pass: ut <- the average of each shell node's
 // copies (local layout; interior entries untouched).
 hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, double* ut, hipStream_t st);

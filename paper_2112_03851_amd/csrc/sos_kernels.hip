@@ -40,17 +40,22 @@ __global__ void k_cg_init(int n_sub, const int32_t* __restrict__ bfirst, const d
 // nodes, quantised to kOrderBins bins of equal width (equal bins in index
 // order). Blocks are dispatched in index order onto compute units as these free
 // up, so when the grid takes several rounds of resident blocks this is list
-// scheduling with the longest jobs first. One workgroup; a counting sort whose
-// ranks inside a chunk come from wave ballots.
+// scheduling with the longest jobs first. One workgroup of NT threads (sm:
+// order_lds_bytes(NT) bytes of LDS); a counting sort whose ranks inside a
+// chunk come from wave ballots.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 64;
+constexpr size_t order_lds_bytes(int nt) {
+  return (size_t)(nt / 64) * sizeof(unsigned long long) + (size_t)kOrderBins * sizeof(int32_t) * (1 + nt / 64);
+}
 
-__global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgScal* __restrict__ scal,
-                                                                TeamSlot* __restrict__ fmap) {
-  constexpr int NW = kOrderThreads / 64;
-  __shared__ unsigned long long wmax[NW];
-  __shared__ int32_t base[kOrderBins];
-  __shared__ int32_t wcnt[NW][kOrderBins];
+template <int NT>
+__device__ void order_blocks(const Dev& d, const CgScal* __restrict__ scal, TeamSlot* __restrict__ fmap,
+                             unsigned char* sm) {
+  constexpr int NW = NT / 64;
+  unsigned long long* wmax = reinterpret_cast<unsigned long long*>(sm);
+  int32_t* base = reinterpret_cast<int32_t*>(wmax + NW);
+  int32_t(*wcnt)[kOrderBins] = reinterpret_cast<int32_t(*)[kOrderBins]>(base + kOrderBins);
   const int n = d.geo.n_sub;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   auto cost = [&](int s) -> unsigned long long {
@@ -59,10 +64,10 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
     return (unsigned long long)(max(scal[s].iters, 0) + 1) * nodes;
   };
   // the first chunk's costs stay in registers (one subdomain per thread for
-  // up to kOrderThreads subdomains: each cost is read once)
+  // up to NT subdomains: each cost is read once)
   const unsigned long long cost0 = tid < n ? cost(tid) : 0ull;
   unsigned long long m = max(cost0, 1ull);
-  for (int s = tid + kOrderThreads; s < n; s += kOrderThreads) m = max(m, cost(s));
+  for (int s = tid + NT; s < n; s += NT) m = max(m, cost(s));
   for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o, 64));
   if (tid < kOrderBins) base[tid] = 0;
   if (lane == 0) wmax[w] = m;
@@ -72,7 +77,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
   const double bsc = double(kOrderBins - 1) / double(mx);
   auto bin_of = [&](unsigned long long c) { return kOrderBins - 1 - min((int)(double(c) * bsc), kOrderBins - 1); };
   auto bin = [&](int s) { return bin_of(s == tid ? cost0 : cost(s)); };
-  for (int s = tid; s < n; s += kOrderThreads) atomicAdd(&base[bin(s)], 1);
+  for (int s = tid; s < n; s += NT) atomicAdd(&base[bin(s)], 1);
   __syncthreads();
   if (tid == 0) {  // counts -> first position of each bin
     int acc = 0;
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
     }
   }
   __syncthreads();
-  for (int c0 = 0; c0 < n; c0 += kOrderThreads) {
+  for (int c0 = 0; c0 < n; c0 += NT) {
     const int s = c0 + tid;
     const int k = s < n ? bin(s) : -1;
     wcnt[w][lane] = 0;
@@ -114,6 +119,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
   }
 }
 
+__global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgScal* __restrict__ scal,
+                                                                TeamSlot* __restrict__ fmap) {
+  __shared__ __align__(16) unsigned char sm[order_lds_bytes(kOrderThreads)];
+  order_blocks<kOrderThreads>(d, scal, fmap, sm);
+}
+
 // ---------------------------------------------------------------------------- exchange
 
 // Position of face F's nodes in the concatenated local vectors: node (a, b)
@@ -126,11 +137,25 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
 // with M_F = Ma (x) Mb and K_F = Ka (x) Mb + Ma (x) Kb (plain 1D factors). The
 // pair's geometry comes resolved from the host (one descriptor load), and the
 // old lambda of a thread's first node is loaded together with the gather.
+// With fmap given, grid row 0 is the block ordering for the fused kernel's
+// next launch (its first block; the row's others exit), which reads only what
+// the fused kernel wrote, and the pairs take rows 1 and up: the ordering runs
+// beside the exchange instead of before it.
 __global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restrict__ pairs, int rows_max,
-                                                         const double* __restrict__ u, double* __restrict__ lam) {
+                                                         const double* __restrict__ u, double* __restrict__ lam,
+                                                         Dev d, const CgScal* __restrict__ scal,
+                                                         TeamSlot* __restrict__ fmap) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* Us = reinterpret_cast<double*>(smem);
-  const ExPair P = pairs[blockIdx.y];
+  int pair = blockIdx.y;
+  if (fmap) {
+    if (pair == 0) {
+      if (blockIdx.x == 0) order_blocks<kExThreads>(d, scal, fmap, smem);
+      return;
+    }
+    --pair;
+  }
+  const ExPair P = pairs[pair];
   const int na = P.na, nb = P.nb;
   const int b0 = blockIdx.x * rows_max;
   if (b0 >= nb) return;
@@ -668,12 +693,14 @@ hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap,
 }
 
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
-                           double* lam, hipStream_t st) {
-  if (n_pairs == 0) return hipSuccess;
+                           double* lam, hipStream_t st, const Dev* d, const CgScal* scal, TeamSlot* fmap) {
+  if (n_pairs == 0) return fmap ? launch_order_blocks(*d, scal, fmap, st) : hipSuccess;
+  if (fmap && (!d || !scal)) return hipErrorInvalidValue;
   const int rows = exchange_rows(max_na);
-  const size_t lds = 2 * sizeof(double) * (size_t)(max_na + 4) * (size_t)(rows + 4);
-  hipLaunchKernelGGL(k_exchange, dim3((max_nb + rows - 1) / rows, n_pairs), dim3(kExThreads), lds, st, pairs, rows, u,
-                     lam);
+  size_t lds = 2 * sizeof(double) * (size_t)(max_na + 4) * (size_t)(rows + 4);
+  if (fmap) lds = std::max(lds, order_lds_bytes(kExThreads));
+  hipLaunchKernelGGL(k_exchange, dim3((max_nb + rows - 1) / rows, n_pairs + (fmap ? 1 : 0)), dim3(kExThreads), lds, st,
+                     pairs, rows, u, lam, fmap ? *d : Dev{}, scal, fmap);
   return hipGetLastError();
 }
 

@@ -110,6 +110,10 @@ struct sos_ctx {
   // workspaces
   double *u = nullptr, *f = nullptr, *lam = nullptr, *ut = nullptr, *rho = nullptr;
   double* b = nullptr;  // local right-hand side f_s + sum_j R_sj^T lambda_{s<-j}
+  // f and b on the x-boundary nodes (i = 0, n0 - 1) of every subdomain,
+  // contiguous per face (SubDesc::xoff); b there is not used
+  double *fxf = nullptr, *bxf = nullptr;
+  int64_t n_xface = 0;
   void *r = nullptr, *x = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   void *r1 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr;  // fused CG only
   double* part = nullptr;       // 3 per segmented block
@@ -169,6 +173,7 @@ void release(sos_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (auto e : c->gevents) (void)hipEventDestroy(e);
   void* ptrs[] = {c->d_subs, c->d_faces, c->d_expairs, c->d_fmap, c->seg.d_blocks, c->seg.d_bfirst, c->u, c->f, c->b,
+                  c->fxf, c->bxf,
                   c->lam, c->ut, c->rho, c->r, c->x, c->p0, c->p1, c->q, c->r1, c->w1, c->s0, c->s1,
                   c->part, c->part_norm, c->d_res, c->psi, c->team_part,
                   c->scal, c->ndone, c->counters, c->flags};
@@ -632,16 +637,26 @@ hipError_t upload_expairs(sos_ctx* c) {
     ExPair P{};
     const int ax = F.axis, ta = ax == 0 ? 1 : 0, tb = ax == 2 ? 1 : 2;
     // strides of the global axes in each side's local layout
-    auto place = [&](const FaceDesc& X, int64_t* base, int64_t* sa, int64_t* sb) {
+    // and, for a face normal to the side's local axis 0, base and strides in
+    // the x-boundary arrays (node (j, k) at xoff + side n1 n2 + j + n1 k;
+    // one node thick: the i = 0 half)
+    auto place = [&](const FaceDesc& X, int64_t* base, int64_t* sa, int64_t* sb, int64_t* xb, int64_t* xsa,
+                     int64_t* xsb) {
       const SubDesc& sd = c->subs[X.s];
       const int64_t st[3] = {1, sd.n[0], (int64_t)sd.n[0] * sd.n[1]};
       *sa = st[sd.iperm[ta]];
       *sb = st[sd.iperm[tb]];
       const int la = sd.iperm[ax];
       *base = sd.off + (int64_t)(X.side ? sd.n[la] - 1 : 0) * st[la];
+      *xb = *xsa = *xsb = -1;
+      if (la == 0) {
+        *xsa = *sa / sd.n[0];
+        *xsb = *sb / sd.n[0];
+        *xb = sd.xoff + ((X.side && sd.n[0] > 1) ? (int64_t)sd.n[1] * sd.n[2] : 0);
+      }
     };
-    place(F, &P.base_s, &P.sa_s, &P.sb_s);
-    place(G, &P.base_j, &P.sa_j, &P.sb_j);
+    place(F, &P.base_s, &P.sa_s, &P.sb_s, &P.xb_s, &P.xsa_s, &P.xsb_s);
+    place(G, &P.base_j, &P.sa_j, &P.sb_j, &P.xb_j, &P.xsa_j, &P.xsb_j);
     const SubDesc& sd = c->subs[F.s];
     P.lam_f = F.lam_off;
     P.lam_g = G.lam_off;
@@ -721,8 +736,9 @@ FusedArgs fused_args(sos_ctx* c) {
   return a;
 }
 
-// b = f on every node; the face-sum kernel, run before every residual, then
-// adds the Robin data on the boundary shell (b = f + sum_j R^T lambda there).
+// b = f on every node; a run starts by adding the Robin data on the boundary
+// shell (b = f + sum_j R^T lambda there), then every exchange rewrites b at
+// the face nodes and every residual at the edges and corners.
 hipError_t copy_load_to_rhs(sos_ctx* c) {
   return hipMemcpyAsync(c->b, c->f, c->n_local * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
 }
@@ -736,15 +752,16 @@ bool schedule_by_work(const sos_ctx* c) {
 
 int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   hipStream_t st = c->stream;
-  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
+  HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->bxf, c->r, c->part,
                          c->fused_team > 1 ? c->team_part : nullptr, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c), st));
   if (ev1) HIPCHK(hipEventRecord(ev1, st));
   // the block ordering runs inside the exchange launch (one more workgroup)
   const bool order = schedule_by_work(c);
-  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st,
-                         order ? &c->dev : nullptr, order ? c->scal : nullptr, order ? c->d_fmap : nullptr));
+  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, c->f,
+                         c->b, c->fxf, c->bxf, st, order ? &c->dev : nullptr, order ? c->scal : nullptr,
+                         order ? c->d_fmap : nullptr));
   return SOS_OK;
 }
 
@@ -752,7 +769,7 @@ int enqueue_batched_iteration(sos_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
 int stepwise_iteration(sos_ctx* c) {
   hipStream_t st = c->stream;
   const SegLaunch& L = c->seg.L;
-  HIPCHK(launch_residual(c->dev, L, c->fp32, true, c->u, c->f, c->lam, c->b, c->r, c->part, nullptr, st));
+  HIPCHK(launch_residual(c->dev, L, c->fp32, true, c->u, c->f, c->lam, c->b, c->bxf, c->r, c->part, nullptr, st));
   HIPCHK(launch_cg_init(c->dev, L, c->part, c->opts.inner_tol, c->opts.inner_abs, c->scal, c->ndone, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.timing) {
@@ -789,7 +806,8 @@ int stepwise_iteration(sos_ctx* c) {
     (void)hipEventDestroy(e1);
   }
   HIPCHK(launch_add_correction(c->dev, L, c->fp32, c->u, c->x, c->scal, st));
-  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, st));
+  HIPCHK(launch_exchange(c->d_expairs, (int32_t)c->pairs.size(), c->max_face_na, c->max_face_nb, c->u, c->lam, c->f,
+                         c->b, c->fxf, c->bxf, st));
   return SOS_OK;
 }
 
@@ -864,6 +882,8 @@ int run_outer(sos_ctx* c, double tol, int max_outer, sos_stats* stats, bool* con
     int rc = zero_directions(c);
     if (rc) return rc;
   }
+  // lambda may have changed since the last exchange (state set, new load)
+  HIPCHK(launch_shell_rhs(c->dev, c->seg.L, c->f, c->lam, c->b, c->fxf, c->bxf, st));
   c->h_res[1] = 0.0;
   c->kernel_ms = 0.0;
   c->kernel_launches = 0;
@@ -1046,7 +1066,7 @@ int autotune(sos_ctx* c) {
     if (rc) return rc;
     for (int rep = 0; rep < 3; ++rep) {
       HIPCHK(launch_fill(c->u, c->n_local, 0.0, st));
-      HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->r, c->part,
+      HIPCHK(launch_residual(c->dev, c->seg.L, c->fp32, false, c->u, c->f, c->lam, c->b, c->bxf, c->r, c->part,
                              c->fused_team > 1 ? c->team_part : nullptr, st));
       HIPCHK(hipEventRecord(e0, st));
       if (launch_fused_cg(c->dev, c->seg.L, c->fp32, c->fused_threads, c->fused_cpt, c->fused_lds, fused_args(c),
@@ -1324,6 +1344,11 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
     g.n_sub = ns * copies;
     g.copies = copies;
   }
+  // x-boundary right-hand sides (local axis order): 2 n1 n2 values each
+  for (auto& d : c->subs) {
+    d.xoff = c->n_xface;
+    c->n_xface += 2 * (int64_t)d.n[1] * d.n[2];
+  }
   rc = apply_robin(c, robin);
   if (rc) {
     release(c);
@@ -1374,7 +1399,8 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
       (rc = dalloc(&c->d_expairs, c->pairs.size())) || (rc = dalloc(&c->d_fmap, c->fmap_cap)) ||
       (rc = dalloc(&c->seg.d_blocks, c->seg.blocks.size())) || (rc = dalloc(&c->seg.d_bfirst, c->seg.bfirst.size())) ||
       (rc = dalloc(&c->u, c->n_local)) || (rc = dalloc(&c->f, c->n_local)) || (rc = dalloc(&c->lam, c->n_lam)) ||
-      (rc = dalloc(&c->b, c->n_local)) ||
+      (rc = dalloc(&c->b, c->n_local)) || (rc = dalloc(&c->fxf, c->n_xface)) ||
+      (rc = dalloc(&c->bxf, c->n_xface)) ||
       (rc = dalloc(&c->ut, c->n_local)) || (rc = dalloc(&c->rho, c->n_local)) ||
       (rc = dalloc_v(&c->r, c->n_local * es)) || (rc = dalloc_v(&c->x, c->n_local * es)) ||
       (rc = dalloc_v(&c->p0, c->n_local * es)) || (rc = dalloc_v(&c->p1, c->n_local * es)) ||
@@ -1423,6 +1449,8 @@ int sos_setup_batch(const sos_mesh* mesh, const sos_partition* part, int32_t cop
     e = hipMemcpy(c->seg.d_bfirst, c->seg.bfirst.data(), c->seg.bfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->f, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->b, 0, c->n_local * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->fxf, 0, c->n_xface * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->bxf, 0, c->n_xface * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->u, 0, c->n_local * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->lam, 0, std::max<int64_t>(1, c->n_lam) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->rho, 0, c->n_local * sizeof(double));

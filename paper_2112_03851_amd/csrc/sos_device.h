@@ -364,6 +364,15 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       return fetch(li, coh_of(kq));
   };
   using Raw = decltype(fetch_at(0, 0));
+  // operand of slot m at plane kc from its loads: make(raw, li, own, edge,
+  // dinv), or with the node's local coordinates (i, j, kc) appended
+  auto make_at = [&](const Raw& rv, int m, int kc, bool own) {
+    const uint32_t li = uint32_t(sl.c[m] + sl.S * kc);
+    if constexpr (std::is_invocable_v<MakeF&, Raw, uint32_t, bool, bool, T, int, int, int>)
+      return make(rv, li, own, edge_of(kc), dinv_of(m, kc), sl.i[m], sl.j[m], kc);
+    else
+      return make(rv, li, own, edge_of(kc), dinv_of(m, kc));
+  };
   // first operand plane of the march: two below the segment, or (uniform z)
   // the subdomain's first plane when the segment starts there, since planes
   // outside the subdomain contribute nothing
@@ -420,7 +429,7 @@ __device__ __forceinline__ void zmarch(const Slots<T, CPT, Q>& sl, T* lds, Fetch
       // subdomain, with own = false): its stores are off, its result unused
       const int kc = min(max(kp[m], 0), sl.nz - 1);
       const bool own = sl.act[m] && kp[m] >= zlo(m) && kp[m] < zhi(m);
-      const auto mv = make(raw[m][U], uint32_t(sl.c[m] + sl.S * kc), own, edge_of(kc), dinv_of(m, kc));
+      const auto mv = make_at(raw[m][U], m, kc, own);
       if (inr[m]) lds[sl.lp[m] + po] = T(op_of(mv));
       // a plane outside the subdomain is never stored, so its carry is unused
       pr[m][2] = T(carry_of(mv));
@@ -589,13 +598,33 @@ __device__ __forceinline__ unsigned long long fused_bytes(const SubDesc& sd, int
 
 // ---------------------------------------------------------------------------- outer kernels
 
+// Index of x-boundary node (i = 0 or n0 - 1, j, k) of subdomain sd in the
+// x-boundary arrays (a subdomain one node thick along x uses the i = 0 half).
+__device__ __forceinline__ int64_t xface_at(const SubDesc& sd, int i, int j, int k) {
+  return sd.xoff + (i == 0 ? 0 : (int64_t)sd.n[1] * sd.n[2]) + j + (int64_t)sd.n[1] * k;
+}
+
+// Right-hand side at a boundary-shell node: bx (and fx = f, if given) on the
+// x-boundary nodes, b elsewhere.
+__device__ __forceinline__ void put_rhs(const SubDesc& sd, int i, int j, int64_t idx, int k, double fv, double v,
+                                        double* __restrict__ b, double* __restrict__ fx, double* __restrict__ bx) {
+  if (i == 0 || i == sd.n[0] - 1) {
+    const int64_t xi = xface_at(sd, i, j, k);
+    bx[xi] = v;
+    if (fx) fx[xi] = fv;
+  } else {
+    b[idx] = v;
+  }
+}
+
 // b = f + sum_j R_sj^T lambda_{s<-j} on the boundary-shell nodes of planes
-// [z0, z1) of subdomain sd (off the shell b = f is left as it is): the z-face
-// planes whole, the other planes' perimeters; every node is written by the
-// block that owns its plane.
+// [z0, z1) of subdomain sd (off the shell b = f is left as it is), and fx = f
+// there on the x-boundary nodes: the z-face planes whole, the other planes'
+// perimeters; every node is written by the block that owns its plane.
 __device__ __forceinline__ void shell_rhs(const Dev& d, const SubDesc& sd, int z0, int z1,
                                           const double* __restrict__ f, const double* __restrict__ lam,
-                                          double* __restrict__ b) {
+                                          double* __restrict__ b, double* __restrict__ fx,
+                                          double* __restrict__ bx) {
   const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2], S = nx * ny;
   const int xs = nx > 1 ? 2 : 1, ys = ny > 1 ? 2 : 1, ix = max(nx - 2, 0);
   const int perim = xs * ny + ys * ix;
@@ -624,20 +653,80 @@ __device__ __forceinline__ void shell_rhs(const Dev& d, const SubDesc& sd, int z
       }
     }
     const int64_t idx = sd.off + i + (int64_t)nx * (j + (int64_t)ny * k);
-    b[idx] = f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz);
+    const double fv = f[idx];
+    put_rhs(sd, i, j, idx, k, fv, fv + lam_terms(L, lam, i, j, k, nx, ny, nz), b, fx, bx);
   }
 }
 
-// r = b - A u with b = f + sum_j R_sj^T lambda_{s<-j}: each block first
-// rewrites b on the shell nodes of its own planes (the march uses b only
-// there, and at its own interior nodes b = f is kept); RZ: also r'D^-1 r (the
+// b = f + sum_j R_sj^T lambda_{s<-j} on the nodes of planes [z0, z1) of
+// subdomain sd that lie on two or more planes of the box's boundary (edges and
+// corners; every node of a plane when the subdomain is one node thick along x
+// or y, of a z-face plane when it is one node thick along z). The exchange
+// writes b at the nodes of one face; only these need the sum of several.
+__device__ __forceinline__ void shell_edges(const Dev& d, const SubDesc& sd, int z0, int z1,
+                                            const double* __restrict__ f, const double* __restrict__ lam,
+                                            double* __restrict__ b, double* __restrict__ bx) {
+  const int nx = sd.n[0], ny = sd.n[1], nz = sd.n[2], S = nx * ny;
+  const bool thin = nx == 1 || ny == 1;
+  // per plane: a z-face plane has its perimeter (or all of it), another plane
+  // its four corner columns (or all of it)
+  const int perim = (thin || nz == 1) ? S : 2 * nx + 2 * (ny - 2);
+  const int inner = thin ? S : 4;
+  const bool lo = z0 == 0, hi = z1 == nz && nz > 1;
+  const int nzf = (lo ? 1 : 0) + (hi ? 1 : 0);
+  const int k0 = lo ? 1 : z0, k1 = hi ? nz - 1 : z1;
+  const int n_face = nzf * perim, total = n_face + max(k1 - k0, 0) * inner;
+  const LamOff L = lam_offsets(d, sd);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int i, j, k, e;
+    bool whole;
+    if (t < n_face) {
+      k = (t < perim && lo) ? 0 : nz - 1;
+      e = t < perim ? t : t - perim;
+      whole = perim == S;
+    } else {
+      const int q = (t - n_face) / inner;
+      k = k0 + q;
+      e = (t - n_face) - q * inner;
+      whole = thin;
+      if (!whole) {  // corner columns
+        i = (e & 1) ? nx - 1 : 0;
+        j = (e & 2) ? ny - 1 : 0;
+      }
+    }
+    if (whole) {
+      i = e % nx;
+      j = e / nx;
+    } else if (t < n_face) {  // perimeter of a z-face plane (nx, ny >= 2)
+      if (e < 2 * ny) {
+        i = e < ny ? 0 : nx - 1;
+        j = e < ny ? e : e - ny;
+      } else {
+        const int e2 = e - 2 * ny, ix = nx - 2;
+        j = e2 < ix ? 0 : ny - 1;
+        i = 1 + (e2 < ix ? e2 : e2 - ix);
+      }
+    }
+    const int64_t idx = sd.off + i + (int64_t)nx * (j + (int64_t)ny * k);
+    put_rhs(sd, i, j, idx, k, 0.0, f[idx] + lam_terms(L, lam, i, j, k, nx, ny, nz), b, nullptr, bx);
+  }
+}
+
+// r = b - A u with b = f + sum_j R_sj^T lambda_{s<-j}. b holds f inside the
+// subdomain, f + lambda on the nodes of one face (written by the exchange, or
+// by k_shell_rhs at the start of a run); each block first rewrites the edge
+// and corner nodes of its own planes, where several faces' data add. On the
+// x-boundary nodes (i = 0, n0 - 1) the right-hand side lives in bx instead, a
+// contiguous array per subdomain face (in b those nodes are one cache line
+// apart, too costly for the exchange to write). RZ: also r'D^-1 r (the
 // stepwise CG's first gamma). ZU: every block marches one segment (the host
 // checks; otherwise the partials are NaN and the solve reports a breakdown).
 template <typename TO, int CPT, bool Q, bool RZ, bool ZU = false>
 __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const BlockDesc* blocks, const double* __restrict__ u,
                                                    const double* __restrict__ f, const double* __restrict__ lam,
-                                                   double* __restrict__ b, TO* __restrict__ r,
-                                                   double* __restrict__ part, double* __restrict__ team_part) {
+                                                   double* __restrict__ b, double* __restrict__ bx,
+                                                   TO* __restrict__ r, double* __restrict__ part,
+                                                   double* __restrict__ team_part) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* lds = reinterpret_cast<double*>(smem);
   // the fused kernel that follows tags its team partials from epoch 0: clear
@@ -646,7 +735,7 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
     for (int i = threadIdx.x; i < d.geo.n_sub * kMaxTeam * 2 * 4; i += blockDim.x) team_part[i] = 0.0;
   const BlockDesc bd = blocks[blockIdx.x];
   const SubDesc sd = d.subs[bd.s];
-  shell_rhs(d, sd, bd.z0, bd.z1, f, lam, b);
+  shell_edges(d, sd, bd.z0, bd.z1, f, lam, b, bx);
   Slots<double, CPT, Q> sl;
   slots_init(sl, sd, d.geo, bd.z0, bd.z1, true);
   lds_zero(lds, sl.G * kPlanes * sl.SP);
@@ -663,7 +752,15 @@ __global__ void __launch_bounds__(Bound<CPT>::value) k_residual(Dev d, const Blo
   // the register allocator would copy every reloaded entry at the loop's end,
   // waiting for all loads in flight)
   auto fetch = [=](uint32_t li, bool) { return at(ub, li); };
-  auto make = [=](double v, uint32_t li, bool, bool, double) { return OpCarry<double>{v, at(bb, li)}; };
+  // the right-hand side of an x-boundary column comes from bx (one address
+  // select per node, one load either way)
+  const int nx1 = sd.n[0] - 1, ny = sd.n[1];
+  const int64_t nynz = (int64_t)sd.n[1] * sd.n[2];
+  const double* __restrict__ xb = bx + sd.xoff;
+  auto make = [=](double v, uint32_t li, bool, bool, double, int i, int j, int k) {
+    const double* p = (i == 0 || i == nx1) ? xb + ((i == 0 ? 0 : nynz) + j + (int64_t)ny * k) : bb + li;
+    return OpCarry<double>{v, *p};
+  };
   auto store = [&](uint32_t li, bool en, bool, int, int, int, double q, double bv, double dinv) {
     if (!en) return;
     const TO rt = TO(bv - q);

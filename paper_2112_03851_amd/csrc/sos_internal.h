@@ -36,6 +36,8 @@ struct SubDesc {
   double qhi[3];    // local: second-order coefficient q at closure node ne2 per axis
   int32_t copy;     // index of the problem copy this subdomain belongs to (batched copies)
   int32_t sbase;    // index of that copy's first subdomain
+  int64_t xoff;     // offset of its x-boundary right-hand side: 2 n1 n2 values, the
+                    // nodes i = 0, then i = n0 - 1, node (j, k) at j + n1 k
 };
 
 // One directed face (s <- j).

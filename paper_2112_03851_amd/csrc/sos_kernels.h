@@ -71,13 +71,14 @@ hipError_t launch_load_density(const Dev& d, int max_n, const double* drho, doub
 // f_s = f_nodes / multiplicity.
 hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, double* f_loc,
                              hipStream_t st);
-// b = f + sum_j R_sj^T lambda_{s<-j} rewritten at the boundary shell nodes
-// (elsewhere b keeps its value, b = f), then r = b - A u (FP64 apply), stored
-// as Tr; partials (r'D^-1 r if rz, else 0), r'r, b'b per block.
-// team_part (optional): the fused kernel's team slots, n_sub * kMaxTeam * 8
-// doubles, cleared for the launch that follows.
+// b = f + sum_j R_sj^T lambda_{s<-j} rewritten at the edge and corner nodes
+// of the boundary shell (the exchange writes the other face nodes; inside,
+// b = f), in bx on the x-boundary nodes (SubDesc::xoff) and in b elsewhere;
+// then r = b - A u (FP64 apply), stored as Tr; partials (r'D^-1 r if rz, else
+// 0), r'r, b'b per block. team_part (optional): the fused kernel's team
+// slots, n_sub * kMaxTeam * 8 doubles, cleared for the launch that follows.
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u,
-                           const double* f, const double* lam, double* b, void* r_out, double* part,
+                           const double* f, const double* lam, double* b, double* bx, void* r_out, double* part,
                            double* team_part, hipStream_t st);
 // Why a subdomain's inner solve stopped early, OR-ed into one device word
 // per solve (the host reads it at every convergence check).
@@ -149,6 +150,9 @@ hipError_t launch_fused_cg(const Dev& d, const SegLaunch& L, int fp32, int threa
 // 1D rows (shared by both sides).
 struct ExPair {
   int64_t base_s, sa_s, sb_s, base_j, sa_j, sb_j;
+  // a side whose face is normal to its local axis 0 keeps its right-hand side
+  // in the x-boundary array (SubDesc::xoff): base and strides there, else -1
+  int64_t xb_s, xsa_s, xsb_s, xb_j, xsa_j, xsb_j;
   int64_t lam_f, lam_g;  // lambda_{s<-j}, lambda_{j<-s}
   double cp, cq;         // p_sj + p_js, q_sj + q_js
   double msa, msb, ksa, ksb;
@@ -164,11 +168,19 @@ inline int exchange_rows(int max_na) {
 // Fused kernel block table (one block per subdomain) ordered by the work of
 // each subdomain's last inner solve, longest first.
 hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap, hipStream_t st);
-// Robin exchange of every interface pair; with fmap (and d, scal) given, the
-// block ordering of launch_order_blocks runs as one more workgroup of it.
+// Robin exchange of every interface pair; with b (and f) given, also
+// b = f + lambda at both sides' face nodes (edge and corner nodes are left to
+// the residual kernel); with fmap (and d, scal) given, the block ordering of
+// launch_order_blocks runs as one more workgroup of it.
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
-                           double* lam, hipStream_t st, const Dev* d = nullptr, const CgScal* scal = nullptr,
-                           TeamSlot* fmap = nullptr);
+                           double* lam, const double* f, double* b, const double* fx, double* bx, hipStream_t st,
+                           const Dev* d = nullptr, const CgScal* scal = nullptr, TeamSlot* fmap = nullptr);
+// b = f + sum_j R^T lambda on every shell node of the segmented launch's
+// blocks, and fx, bx (f and b on the x-boundary nodes, SubDesc::xoff) (the
+// start of a run: the residual kernel itself rewrites only edges and corners,
+// the exchange the rest).
+hipError_t launch_shell_rhs(const Dev& d, const SegLaunch& L, const double* f, const double* lam, double* b,
+                            double* fx, double* bx, hipStream_t st);
 // Global residual check. First pass: ut <- the average of each shell node's
 // copies (local layout; interior entries untouched).
 hipError_t launch_glue_shell(const Dev& d, int max_shell, const double* u, double* ut, hipStream_t st);

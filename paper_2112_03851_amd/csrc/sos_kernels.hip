@@ -125,6 +125,15 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
   order_blocks<kOrderThreads>(d, scal, fmap, sm);
 }
 
+// Every shell node of the block's planes (the state of a run's first
+// residual: lambda may have been set from outside).
+__global__ void __launch_bounds__(1024) k_shell_rhs(Dev d, const BlockDesc* blocks, const double* __restrict__ f,
+                                                    const double* __restrict__ lam, double* __restrict__ b,
+                                                    double* __restrict__ fx, double* __restrict__ bx) {
+  const BlockDesc bd = blocks[blockIdx.x];
+  shell_rhs(d, d.subs[bd.s], bd.z0, bd.z1, f, lam, b, fx, bx);
+}
+
 // ---------------------------------------------------------------------------- exchange
 
 // Position of face F's nodes in the concatenated local vectors: node (a, b)
@@ -137,12 +146,19 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_blocks(Dev d, const CgS
 // with M_F = Ma (x) Mb and K_F = Ka (x) Mb + Ma (x) Kb (plain 1D factors). The
 // pair's geometry comes resolved from the host (one descriptor load), and the
 // old lambda of a thread's first node is loaded together with the gather.
+// With b given, the new data also go into both sides' right-hand sides at the
+// face nodes, b = f + lambda (bx = fx + lambda for a side whose face is
+// normal to its local axis 0): exact wherever a node lies on this face alone;
+// the residual kernel rewrites the edge and corner nodes, where several faces'
+// data add (two exchange blocks may write such a node first).
 // With fmap given, grid row 0 is the block ordering for the fused kernel's
 // next launch (its first block; the row's others exit), which reads only what
 // the fused kernel wrote, and the pairs take rows 1 and up: the ordering runs
 // beside the exchange instead of before it.
 __global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restrict__ pairs, int rows_max,
                                                          const double* __restrict__ u, double* __restrict__ lam,
+                                                         const double* __restrict__ f, double* __restrict__ b,
+                                                         const double* __restrict__ fx, double* __restrict__ bx,
                                                          Dev d, const CgScal* __restrict__ scal,
                                                          TeamSlot* __restrict__ fmap) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -163,11 +179,26 @@ __global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restric
   const int W = na + 4, H = rows + 4;
   double* Uj = Us + W * H;
   const int t0 = threadIdx.x;
-  double lf0 = 0.0, lg0 = 0.0;
+  // right-hand side of face node t of the band on side s and on side j: in
+  // the x-boundary arrays for a face normal to the side's local axis 0
+  const bool xs = P.xb_s >= 0, xj = P.xb_j >= 0;
+  const double* fs_ = xs ? fx + P.xb_s : f + P.base_s;
+  const double* fj_ = xj ? fx + P.xb_j : f + P.base_j;
+  double* bs_ = xs ? bx + P.xb_s : b + P.base_s;
+  double* bj_ = xj ? bx + P.xb_j : b + P.base_j;
+  const int64_t sas = xs ? P.xsa_s : P.sa_s, sbs = xs ? P.xsb_s : P.sb_s;
+  const int64_t saj = xj ? P.xsa_j : P.sa_j, sbj = xj ? P.xsb_j : P.sb_j;
+  auto node_s = [&](int t) { return (t % na) * sas + (b0 + t / na) * sbs; };
+  auto node_j = [&](int t) { return (t % na) * saj + (b0 + t / na) * sbj; };
+  double lf0 = 0.0, lg0 = 0.0, fs0 = 0.0, fj0 = 0.0;
   if (t0 < na * rows) {
     const int64_t t2 = (t0 % na) + (int64_t)na * (b0 + t0 / na);
     lf0 = lam[P.lam_f + t2];
     lg0 = lam[P.lam_g + t2];
+    if (b) {
+      fs0 = fs_[node_s(t0)];
+      fj0 = fj_[node_j(t0)];
+    }
   }
   for (int e = threadIdx.x; e < W * H; e += blockDim.x) {
     const int a = e % W - 2, b = e / W + b0 - 2;
@@ -211,16 +242,26 @@ __global__ void __launch_bounds__(kExThreads) k_exchange(const ExPair* __restric
   if (t0 < na * rows) {
     double as, aj;
     const int64_t t2 = apply(t0, as, aj);
-    lam[P.lam_f + t2] = -lg0 + aj;
-    lam[P.lam_g + t2] = -lf0 + as;
+    const double ls = -lg0 + aj, lj = -lf0 + as;
+    lam[P.lam_f + t2] = ls;
+    lam[P.lam_g + t2] = lj;
+    if (b) {
+      bs_[node_s(t0)] = fs0 + ls;
+      bj_[node_j(t0)] = fj0 + lj;
+    }
   }
   for (int t = t0 + blockDim.x; t < na * rows; t += blockDim.x) {
     double as, aj;
     const int64_t t2 = apply(t, as, aj);
     const double lf = lam[P.lam_f + t2];
     const double lg = lam[P.lam_g + t2];
-    lam[P.lam_f + t2] = -lg + aj;
-    lam[P.lam_g + t2] = -lf + as;
+    const double ls = -lg + aj, lj = -lf + as;
+    lam[P.lam_f + t2] = ls;
+    lam[P.lam_g + t2] = lj;
+    if (b) {
+      bs_[node_s(t)] = fs_[node_s(t)] + ls;
+      bj_[node_j(t)] = fj_[node_j(t)] + lj;
+    }
   }
 }
 
@@ -582,33 +623,33 @@ hipError_t launch_load_nodes(const Dev& d, int max_n, const double* f_nodes, dou
 }
 
 hipError_t launch_residual(const Dev& d, const SegLaunch& L, int fp32, bool rz, const double* u, const double* f,
-                           const double* lam, double* b, void* r_out, double* part, double* team_part,
+                           const double* lam, double* b, double* bx, void* r_out, double* part, double* team_part,
                            hipStream_t st) {
   SOS_DISPATCH_Q(d.hasq, {
   if (fp32 && rz && L.zu) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true, true>), dim3(L.nblocks),
-                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out,
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, bx, (float*)r_out,
                                                part, team_part));
   } else if (fp32 && rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, bx, (float*)r_out, part, team_part));
   } else if (fp32 && L.zu) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false, true>), dim3(L.nblocks),
-                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part,
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, bx, (float*)r_out, part,
                                                team_part));
   } else if (fp32) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<float, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, f, lam, b, (float*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, bx, (float*)r_out, part, team_part));
   } else if (rz && L.zu) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true, true>), dim3(L.nblocks),
-                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b,
+                                               dim3(L.threads), L.lds64, st, d, L.blocks, u, f, lam, b, bx,
                                                (double*)r_out, part, team_part));
   } else if (rz) {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, true>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, f, lam, b, (double*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, bx, (double*)r_out, part, team_part));
   } else {
     SOS_DISPATCH_CPT(L.cpt, hipLaunchKernelGGL((k_residual<double, C, Q, false>), dim3(L.nblocks), dim3(L.threads),
-                                               L.lds64, st, d, L.blocks, u, f, lam, b, (double*)r_out, part, team_part));
+                                               L.lds64, st, d, L.blocks, u, f, lam, b, bx, (double*)r_out, part, team_part));
   }
   });
   return hipGetLastError();
@@ -693,14 +734,21 @@ hipError_t launch_order_blocks(const Dev& d, const CgScal* scal, TeamSlot* fmap,
 }
 
 hipError_t launch_exchange(const ExPair* pairs, int32_t n_pairs, int32_t max_na, int32_t max_nb, const double* u,
-                           double* lam, hipStream_t st, const Dev* d, const CgScal* scal, TeamSlot* fmap) {
+                           double* lam, const double* f, double* b, const double* fx, double* bx, hipStream_t st,
+                           const Dev* d, const CgScal* scal, TeamSlot* fmap) {
   if (n_pairs == 0) return fmap ? launch_order_blocks(*d, scal, fmap, st) : hipSuccess;
-  if (fmap && (!d || !scal)) return hipErrorInvalidValue;
+  if ((fmap && (!d || !scal)) || (b && (!f || !fx || !bx))) return hipErrorInvalidValue;
   const int rows = exchange_rows(max_na);
   size_t lds = 2 * sizeof(double) * (size_t)(max_na + 4) * (size_t)(rows + 4);
   if (fmap) lds = std::max(lds, order_lds_bytes(kExThreads));
   hipLaunchKernelGGL(k_exchange, dim3((max_nb + rows - 1) / rows, n_pairs + (fmap ? 1 : 0)), dim3(kExThreads), lds, st,
-                     pairs, rows, u, lam, fmap ? *d : Dev{}, scal, fmap);
+                     pairs, rows, u, lam, f, b, fx, bx, fmap ? *d : Dev{}, scal, fmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_shell_rhs(const Dev& d, const SegLaunch& L, const double* f, const double* lam, double* b,
+                            double* fx, double* bx, hipStream_t st) {
+  hipLaunchKernelGGL(k_shell_rhs, dim3(L.nblocks), dim3(L.threads), 0, st, d, L.blocks, f, lam, b, fx, bx);
   return hipGetLastError();
 }
 

@@ -58,7 +58,11 @@ static hipError_t fused_launch_one(const Dev& d, const SegLaunch& L, int threads
   const int32_t* bf = L.bfirst;
   FusedArgs aa = a;
   void* args[] = {&dd, &bf, &aa};
-  return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)lds, st);
+  const hipError_t e = hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)lds, st);
+  // the error is returned here: clear HIP's per-thread last error too, or the
+  // next launch check of any problem on this thread would report it again
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
 }
 
 template <int C>

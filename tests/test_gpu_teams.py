@@ -112,3 +112,27 @@ def test_fixed_block_or_team_is_kept_over_a_cached_tuning(tmp_path, monkeypatch)
     prob.close()
     assert st["converged"] and np.all(teams == 2)
     assert len(cache.read_text().splitlines()) == 1
+
+
+def test_team_grid_that_cannot_be_resident_is_refused_and_does_not_leak():
+    """A team grid larger than the GPU holds at once (64 subdomains x 8
+    members of 1024 threads) is refused at launch with SOS_EHIP before any
+    block runs, and the refusal does not reach the next problem's calls."""
+    import torch
+    from paper_2112_03851_amd import sos
+    cuts = tuple(range(4, 32, 4))
+    case = Case((32, 32, 16), cuts=(cuts, cuts, ()), p=256.0)
+    drho = uniform_density(case.ne, seed=3)
+    f, _ = case.density_loads(drho)
+    d = torch.tensor(drho, device="cuda")
+    prob = case.problem(precision="fp32", mode="batched", block=1024, team=8, check_every=5, max_outer=10)
+    with pytest.raises(sos.SosError) as ei:
+        prob.solve(d, 1e-8)
+    prob.close()
+    print("refused:", str(ei.value)[:160], flush=True)
+    assert ei.value.code == sos.SOS_EHIP and "cooperative" in str(ei.value)
+    prob = case.problem(precision="fp32", mode="batched", block=256, team=1, check_every=5, max_outer=20000,
+                        inner_tol=1e-3, inner_abs=0.0)
+    phi, st = prob.solve(d, 1e-8)
+    prob.close()
+    assert st["converged"] and A.residual_norm(case.mesh, phi.cpu().numpy(), f) <= 1e-8 * 1.001

@@ -1056,6 +1056,9 @@ int autotune(sos_ctx* c) {
       if (team_ok(t, -1)) teams.push_back(t);
   hipStream_t st = c->stream;
   if (int rc0 = zero_directions(c)) return rc0;
+  // the trial launches solve the first outer iteration's problem: the
+  // right-hand side on the boundary shell as a run starts it
+  HIPCHK(launch_shell_rhs(c->dev, c->seg.L, c->f, c->lam, c->b, c->fxf, c->bxf, st));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -60,12 +60,20 @@ def test_apply_matches_oracle_subdomain_matrices(name, q):
     prob.close()
 
 
+STEP_CASES = {
+    "cross_points_neumann": dict(ne=(6, 5, 6), bc=(0, 0, 1, 0, 0, 0), cuts=((3,), (2,), (2, 4)), p=11.0),
+    # 33 x 33 node planes: the FP64 kernels at three columns per thread
+    "plane_33x33": dict(ne=(48, 48, 4), cuts=((16, 32), (16, 32), (2,)), p=384.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STEP_CASES))
 @pytest.mark.parametrize("q", [0.0, 0.02])
-def test_one_outer_iteration_matches_oracle_step(q):
+def test_one_outer_iteration_matches_oracle_step(q, name):
     """u^1 = A_s^-1 (f_s + sum R^T lambda^0) and the exchanged lambda^1, from a
     random state, with cross points and Neumann faces (zeroth and second order)."""
     torch = _torch()
-    case = Case((6, 5, 6), bc=(0, 0, 1, 0, 0, 0), cuts=((3,), (2,), (2, 4)), p=11.0)
+    case = Case(**STEP_CASES[name])
     prob = case.problem(precision="fp64", mode="stepwise", inner_abs=1e-14, max_inner=2000, q=q)
     lay = case.check_layout(prob)
     drho = uniform_density(case.ne, seed=2)
